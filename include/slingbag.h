@@ -1,0 +1,162 @@
+/*
+ * slingbag.h - C ABI of the MI355X (gfx950) library for the differentiable
+ * point-cloud photoacoustic forward operator of 4D SlingBAG and its adjoint.
+ *
+ * The problem (paper Sec. 2.1-2.2): a dynamic scene is a cloud of balls, each
+ * with a position mu, a size a0 and a peak initial pressure p0, whose
+ * attributes at normalised frame time t are deformed by Eq. 1 with a
+ * deformation function H(t) (Eq. 2, or a Fourier series).  For every frame,
+ * the pressure trace that each deformed ball radiates is summed into every
+ * sensor's time samples (the "forward"); the predicted frames are compared
+ * with the measured frames by an L2 loss; and the gradient of that loss with
+ * respect to every ball attribute and deformation coefficient drives each
+ * iterative-reconstruction step (the "adjoint").
+ *
+ * Physics used for one ball (the paper cites its radiator without giving it;
+ * this is the textbook solution of the wave equation for a spherically
+ * symmetric initial pressure with zero initial velocity, speed c):
+ *   uniform sphere (radius R, pressure P), sensor at distance r > R:
+ *     p(r, t) = P (r - c t) / (2 r)   for |r - c t| <= R, else 0   (the N-wave)
+ *   Gaussian ball (std a, peak P):
+ *     p(r, t) = P / (2r) [ (r-ct) e^{-(r-ct)^2/2a^2} + (r+ct) e^{-(r+ct)^2/2a^2} ]
+ *   Sample k of a sensor (time t_k = t0 + k/fs) is the mean of p over
+ *   [t_k - 1/(2 fs), t_k + 1/(2 fs)].  Samples with k outside [0, T) are dropped.
+ *   The Gaussian ball's (r + ct) term is below the float range for every
+ *   sensor outside the ball and is not evaluated; its trace is cut where
+ *   |r - c t| exceeds 6 a + c/(2 fs) (relative truncation below 2e-8).
+ *
+ * Deformation (Eq. 1): R_f = R (1 + H^R(t_f)), P_f = P (1 + H^P(t_f)); each
+ * coordinate x_f = x (1 + H^x(t_f)) (SB_POS_MUL, Eq. 1) or x_f = x + H^x(t_f)
+ * (SB_POS_ADD).  H is the Gaussian-basis sum of Eq. 2
+ * (SB_BASIS_GAUSS), a Fourier series sum_k a_k cos(2 pi k t) + b_k sin(2 pi k t)
+ * (SB_BASIS_FOURIER), or zero (SB_BASIS_STATIC).
+ *
+ * Loss (Sec. 2.2, L2 loss): L = 1/2 sum over all frames, sensors, samples of
+ * (y - d)^2; residual = y - d is the gradient of L with respect to y.
+ *
+ * Units: SI (metres, seconds, m/s, Hz).  Memory: every array argument is a
+ * DEVICE pointer owned by the caller (e.g. allocated by PyTorch) unless marked
+ * HOST; the library never frees or keeps caller memory.  All arrays are
+ * contiguous float32 structure-of-arrays:
+ *   balls      [5][B_total]       rows x, y, z, R (radius, or std a), P
+ *   deform     [5][M][B_total]    per attribute x, y, z, R, P: M coefficients
+ *                                 FOURIER: M = 2K, coefficient 2(k-1) multiplies
+ *                                   cos(2 pi k t), 2(k-1)+1 multiplies sin(2 pi k t)
+ *                                 GAUSS:   M = 3N, coefficient 3n is w_n, 3n+1
+ *                                   theta_n, 3n+2 sigma_n (Eq. 2)
+ *   frame_t    [F_total]          normalised frame times
+ *   sensors    [3][S]             rows x, y, z
+ *   signals, measured, residual   [F_total][S][T]
+ * A batch is n_scenes independent scenes, concatenated: scene i owns balls
+ * [ball_offset[i], ball_offset[i+1]) and frames [frame_offset[i],
+ * frame_offset[i+1]); all scenes share the sensors, c, fs, t0 and T.
+ *
+ * Calls are asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ * Host-side validation runs before anything is enqueued; an invalid argument
+ * returns a negative status and enqueues nothing.  Conditions that only the
+ * device can see (a sensor inside a uniform ball, a non-finite or
+ * non-positive deformed size, a negative deformed pressure) skip the affected
+ * ball and raise a sticky device flag, read back by slingbag_check().
+ * Entry points are safe to call from several host threads on distinct
+ * streams.
+ */
+#ifndef SLINGBAG_H
+#define SLINGBAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes (returned by every entry point) ---- */
+#define SB_OK               0
+#define SB_ERR_INVALID_ARG  (-1)   /* null pointer, unknown enum, bad scalar */
+#define SB_ERR_SHAPE        (-2)   /* offsets not a prefix sum, too many scenes/terms, size overflow */
+#define SB_ERR_NONFINITE    (-3)   /* non-finite c, fs or t0 */
+#define SB_ERR_GEOMETRY     (-4)   /* reserved for geometry errors found on the host */
+#define SB_ERR_HIP          (-5)   /* a HIP runtime call failed (message in slingbag_last_error) */
+#define SB_ERR_DEVICE_FLAG  (-6)   /* slingbag_check found a device-side violation */
+#define SB_ERR_UNSUPPORTED  (-7)   /* valid request this build does not implement */
+
+/* ---- device flag bits (slingbag_check) ---- */
+#define SB_FLAG_GEOMETRY    1u     /* a sensor lay inside a uniform ball (pair skipped) */
+#define SB_FLAG_NONFINITE   2u     /* a deformed attribute was non-finite, R_f <= 0 or P_f < 0 (ball skipped) */
+#define SB_FLAG_CLIPPED     4u     /* some trace fell partly outside [0, T) (dropped; informational) */
+
+/* ---- enums ---- */
+#define SB_KERNEL_UNIFORM   0      /* uniform sphere of radius R */
+#define SB_KERNEL_GAUSS     1      /* Gaussian ball of std R (Sec. 2.1) */
+#define SB_BASIS_STATIC     0      /* H = 0 */
+#define SB_BASIS_FOURIER    1      /* H = sum_k a_k cos 2 pi k t + b_k sin 2 pi k t */
+#define SB_BASIS_GAUSS      2      /* H = sum_n w_n exp(-(t - theta_n)^2 / (2 sigma_n^2)), Eq. 2 */
+#define SB_POS_ADD          0      /* x_f = x + H^x(t) */
+#define SB_POS_MUL          1      /* x_f = x (1 + H^x(t)), Eq. 1 */
+
+/* ---- limits ---- */
+#define SB_MAX_SCENES       32
+#define SB_MAX_FOURIER      8      /* harmonics K */
+#define SB_MAX_GAUSS_BASES  16     /* bases N per attribute */
+
+typedef struct sb_config {
+    int32_t kernel;      /* SB_KERNEL_* */
+    int32_t basis;       /* SB_BASIS_* */
+    int32_t pos_mode;    /* SB_POS_* */
+    int32_t n_terms;     /* K (FOURIER) or N (GAUSS); ignored for STATIC */
+    int32_t n_sensors;   /* S >= 1 */
+    int32_t n_samples;   /* 1 <= T <= 2^28 */
+    double  c;           /* speed of sound, > 0 */
+    double  fs;          /* sample rate, > 0 */
+    double  t0;          /* time of sample 0, finite */
+} sb_config;
+
+typedef struct sb_batch {
+    int32_t        n_scenes;      /* 1 .. SB_MAX_SCENES */
+    int32_t        reserved;      /* must be 0 */
+    const int64_t* ball_offset;   /* HOST [n_scenes+1], ball_offset[0] = 0, non-decreasing */
+    const int64_t* frame_offset;  /* HOST [n_scenes+1], frame_offset[0] = 0, non-decreasing */
+} sb_batch;
+
+/* Forward operator (Sec. 2.2: the radiator applied to each ball's time-varying
+ * attributes, Eq. 1-2).  Writes signals[f][s][k] = sum over the balls of f's
+ * scene of the sampled trace of that ball at sensor s (every entry is
+ * overwritten; frames of empty scenes become zero).  deform may be NULL only
+ * for SB_BASIS_STATIC.  Scratch: none beyond a per-device flag word. */
+int slingbag_forward(const sb_config* cfg, const sb_batch* batch,
+                     const float* balls, const float* deform, const float* frame_t,
+                     const float* sensors, float* signals, void* stream);
+
+/* L2 data loss (Sec. 2.2).  residual[i] = signals[i] - measured[i] for all
+ * F_total*S*T entries (residual may alias signals or measured), and *loss
+ * (a DEVICE double) = 1/2 sum residual^2, reduced in a fixed order (the
+ * result does not depend on timing).  Scratch: a per-device buffer of block
+ * partials, allocated on first use and grown as needed. */
+int slingbag_loss(const sb_config* cfg, const sb_batch* batch,
+                  const float* signals, const float* measured, float* residual,
+                  double* loss, void* stream);
+
+/* Adjoint (Sec. 2.2: gradient of the L2 loss with respect to all baseline
+ * attributes and deformation parameters).  Given residual = dL/dsignals,
+ * writes grad_balls [5][B_total] = dL/dballs and grad_deform [5][M][B_total]
+ * = dL/ddeform (both overwritten; grad_deform may be NULL only for STATIC).
+ * Per-frame deformed attributes are recomputed here, never stored. */
+int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch,
+                     const float* balls, const float* deform, const float* frame_t,
+                     const float* sensors, const float* residual,
+                     float* grad_balls, float* grad_deform, void* stream);
+
+/* Waits for `stream`, returns the device flag bits raised since the last
+ * check in *flags (HOST, may be NULL) and clears them.  Returns
+ * SB_ERR_DEVICE_FLAG if SB_FLAG_GEOMETRY or SB_FLAG_NONFINITE was raised. */
+int slingbag_check(void* stream, uint32_t* flags);
+
+/* Message for the last non-OK status returned on the calling host thread. */
+const char* slingbag_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int slingbag_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLINGBAG_H */

@@ -1,0 +1,169 @@
+"""ctypes binding of libslingbag.so (include/slingbag.h), argument marshalling only.
+
+The functions here take raw device addresses (ints) and host offset arrays and
+call the C entry points of the same names; every step of the operator runs in
+the library's HIP kernels.  Loading fails loudly when the library is missing:
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libslingbag.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "slingbag.h")
+
+# status codes and enums, mirrored from include/slingbag.h
+SB_OK = 0
+SB_ERR_INVALID_ARG = -1
+SB_ERR_SHAPE = -2
+SB_ERR_NONFINITE = -3
+SB_ERR_GEOMETRY = -4
+SB_ERR_HIP = -5
+SB_ERR_DEVICE_FLAG = -6
+SB_ERR_UNSUPPORTED = -7
+SB_FLAG_GEOMETRY, SB_FLAG_NONFINITE, SB_FLAG_CLIPPED = 1, 2, 4
+SB_MAX_SCENES = 32
+
+
+class SlingbagError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"slingbag status {status}: {message}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("pos_mode", ctypes.c_int32), ("n_terms", ctypes.c_int32),
+                ("n_sensors", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("c", ctypes.c_double), ("fs", ctypes.c_double), ("t0", ctypes.c_double)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_scenes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ball_offset", ctypes.POINTER(ctypes.c_int64)),
+                ("frame_offset", ctypes.POINTER(ctypes.c_int64))]
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "slingbag_forward": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP, _VP],
+    "slingbag_loss": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP],
+    "slingbag_adjoint": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP,
+                         _VP, _VP, _VP],
+    "slingbag_check": [_VP, ctypes.POINTER(ctypes.c_uint32)],
+    "slingbag_last_error": [],
+    "slingbag_version": [],
+}
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/slingbag.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slingbag_\w+)\s*\(", text)))
+
+
+def load():
+    """Load libslingbag.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_03898_amd.build`"
+                           " (the operator has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "slingbag_last_error" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().slingbag_last_error().decode()
+
+
+def _check(status: int):
+    if status != SB_OK:
+        raise SlingbagError(status, last_error())
+
+
+class Problem:
+    """Static description of a batch: physics config plus host offset arrays.
+
+    Holds the ctypes structures so that repeated calls marshal nothing new.
+    """
+
+    def __init__(self, kernel, basis, pos_mode, n_terms, n_sensors, n_samples, c, fs, t0,
+                 ball_offset, frame_offset):
+        self.cfg = Config(int(kernel), int(basis), int(pos_mode), int(n_terms), int(n_sensors),
+                          int(n_samples), float(c), float(fs), float(t0))
+        self.ball_offset = np.ascontiguousarray(np.asarray(ball_offset, dtype=np.int64))
+        self.frame_offset = np.ascontiguousarray(np.asarray(frame_offset, dtype=np.int64))
+        n = len(self.ball_offset) - 1
+        if n < 1 or len(self.frame_offset) != n + 1:
+            raise ValueError("ball_offset and frame_offset must both have n_scenes+1 entries")
+        self.batch = Batch(n, 0, self.ball_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           self.frame_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.kernel, wl.basis, wl.pos_mode, wl.n_terms, wl.sensors.shape[1], wl.n_samples,
+                   wl.c, wl.fs, wl.t0, wl.ball_offset, wl.frame_offset)
+
+    @property
+    def n_balls(self) -> int:
+        return int(self.ball_offset[-1])
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.frame_offset[-1])
+
+    @property
+    def n_coef(self) -> int:
+        b, n = self.cfg.basis, self.cfg.n_terms
+        return 0 if b == 0 else (2 * n if b == 1 else 3 * n)
+
+    def pairs(self) -> int:
+        bo, fo = self.ball_offset, self.frame_offset
+        return int(((bo[1:] - bo[:-1]) * (fo[1:] - fo[:-1])).sum()) * int(self.cfg.n_sensors)
+
+
+def forward(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, signals: int,
+            stream: int = 0):
+    _check(load().slingbag_forward(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), balls, deform,
+                                   frame_t, sensors, signals, stream))
+
+
+def loss(pb: Problem, signals: int, measured: int, residual: int, loss_out: int, stream: int = 0):
+    _check(load().slingbag_loss(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), signals, measured,
+                                residual, loss_out, stream))
+
+
+def adjoint(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, residual: int,
+            grad_balls: int, grad_deform: int, stream: int = 0):
+    _check(load().slingbag_adjoint(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), balls, deform,
+                                   frame_t, sensors, residual, grad_balls, grad_deform, stream))
+
+
+def check(stream: int = 0) -> int:
+    """Wait for the stream; return the device flag bits (raises on geometry/non-finite flags)."""
+    flags = ctypes.c_uint32(0)
+    st = load().slingbag_check(stream, ctypes.byref(flags))
+    if st != SB_OK:
+        raise SlingbagError(st, last_error())
+    return int(flags.value)
+
+
+def version() -> int:
+    return int(load().slingbag_version())

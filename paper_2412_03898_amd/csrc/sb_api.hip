@@ -1,0 +1,270 @@
+// Host side of the C ABI: argument validation, work decomposition, per-device
+// workspace and error reporting.  Every check here runs before anything is
+// enqueued, so an invalid call leaves the device untouched.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sb_internal.hpp"
+
+namespace sb {
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+// Per-device scratch: the sticky flag word and the loss partials.
+struct DeviceState {
+    unsigned* flags = nullptr;
+    double* partials = nullptr;
+};
+
+static std::mutex g_mu;
+static std::vector<DeviceState> g_dev;
+
+static int device_state(DeviceState** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(SB_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    DeviceState& ds = g_dev[dev];
+    if (!ds.flags) {
+        e = hipMalloc(&ds.flags, 256);
+        if (e != hipSuccess) return fail(SB_ERR_HIP, "hipMalloc(flags): %s", hipGetErrorString(e));
+        e = hipMemset(ds.flags, 0, 256);
+        if (e != hipSuccess) return fail(SB_ERR_HIP, "hipMemset(flags): %s", hipGetErrorString(e));
+        e = hipMalloc(&ds.partials, sizeof(double) * loss_blocks());
+        if (e != hipSuccess) return fail(SB_ERR_HIP, "hipMalloc(partials): %s", hipGetErrorString(e));
+    }
+    *out = &ds;
+    return SB_OK;
+}
+
+// ---- validation ----
+struct Shape {
+    int64_t B = 0, F = 0, S = 0, T = 0;
+    int M = 0;
+};
+
+static int validate_config(const sb_config* cfg, Shape& sh) {
+    if (!cfg) return fail(SB_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->kernel != SB_KERNEL_UNIFORM && cfg->kernel != SB_KERNEL_GAUSS)
+        return fail(SB_ERR_INVALID_ARG, "unknown kernel %d", cfg->kernel);
+    if (cfg->basis < SB_BASIS_STATIC || cfg->basis > SB_BASIS_GAUSS)
+        return fail(SB_ERR_INVALID_ARG, "unknown basis %d", cfg->basis);
+    if (cfg->pos_mode != SB_POS_ADD && cfg->pos_mode != SB_POS_MUL)
+        return fail(SB_ERR_INVALID_ARG, "unknown pos_mode %d", cfg->pos_mode);
+    if (cfg->basis == SB_BASIS_FOURIER && (cfg->n_terms < 1 || cfg->n_terms > SB_MAX_FOURIER))
+        return fail(SB_ERR_SHAPE, "n_terms %d outside 1..%d for the Fourier basis", cfg->n_terms, SB_MAX_FOURIER);
+    if (cfg->basis == SB_BASIS_GAUSS && (cfg->n_terms < 1 || cfg->n_terms > SB_MAX_GAUSS_BASES))
+        return fail(SB_ERR_SHAPE, "n_terms %d outside 1..%d for the Gaussian basis", cfg->n_terms,
+                    SB_MAX_GAUSS_BASES);
+    if (cfg->n_sensors < 1) return fail(SB_ERR_SHAPE, "n_sensors must be >= 1 (got %d)", cfg->n_sensors);
+    if (cfg->n_samples < 1 || cfg->n_samples > (1 << 28))
+        return fail(SB_ERR_SHAPE, "n_samples must be in 1..2^28 (got %d)", cfg->n_samples);
+    if (!isfinite(cfg->c) || !isfinite(cfg->fs) || !isfinite(cfg->t0))
+        return fail(SB_ERR_NONFINITE, "c, fs and t0 must be finite");
+    if (!(cfg->c > 0.0) || !(cfg->fs > 0.0)) return fail(SB_ERR_INVALID_ARG, "c and fs must be > 0");
+    sh.S = cfg->n_sensors;
+    sh.T = cfg->n_samples;
+    sh.M = cfg->basis == SB_BASIS_FOURIER ? 2 * cfg->n_terms
+         : cfg->basis == SB_BASIS_GAUSS   ? 3 * cfg->n_terms : 0;
+    return SB_OK;
+}
+
+static int validate_batch(const sb_batch* batch, Shape& sh) {
+    if (!batch) return fail(SB_ERR_INVALID_ARG, "batch is NULL");
+    if (batch->n_scenes < 1 || batch->n_scenes > SB_MAX_SCENES)
+        return fail(SB_ERR_SHAPE, "n_scenes %d outside 1..%d", batch->n_scenes, SB_MAX_SCENES);
+    if (batch->reserved != 0) return fail(SB_ERR_INVALID_ARG, "batch.reserved must be 0");
+    if (!batch->ball_offset || !batch->frame_offset)
+        return fail(SB_ERR_INVALID_ARG, "ball_offset / frame_offset is NULL");
+    if (batch->ball_offset[0] != 0 || batch->frame_offset[0] != 0)
+        return fail(SB_ERR_SHAPE, "offsets must start at 0");
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        if (batch->ball_offset[i + 1] < batch->ball_offset[i] ||
+            batch->frame_offset[i + 1] < batch->frame_offset[i])
+            return fail(SB_ERR_SHAPE, "offsets of scene %d decrease", i);
+        if (batch->ball_offset[i + 1] - batch->ball_offset[i] > (int64_t)INT32_MAX - 4096)
+            return fail(SB_ERR_SHAPE, "scene %d has too many balls", i);
+    }
+    sh.B = batch->ball_offset[batch->n_scenes];
+    sh.F = batch->frame_offset[batch->n_scenes];
+    if (sh.F > (int64_t)INT32_MAX) return fail(SB_ERR_SHAPE, "too many frames");
+    if (sh.T > 0 && sh.S > 0 && sh.F > (int64_t)(INT64_MAX / 8) / (sh.S * sh.T))
+        return fail(SB_ERR_SHAPE, "signal size overflows");
+    return SB_OK;
+}
+
+// Tile configuration per trace kernel (balls per group, waves per block, tile length).
+static TileCfg pick_tiles(int kernel) {
+    TileCfg tc;
+    if (kernel == SB_KERNEL_UNIFORM) { tc.nw = 4; tc.g = 128; tc.ucap = 64; }
+    else { tc.nw = 4; tc.g = 128; tc.ucap = 96; }
+    return tc;
+}
+
+static void fill_params(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh,
+                        const TileCfg& tc) {
+    memset(&p, 0, sizeof p);
+    p.B = sh.B;
+    p.S = (int32_t)sh.S;
+    p.T = (int32_t)sh.T;
+    p.basis = cfg->basis;
+    p.pos_mode = cfg->pos_mode;
+    p.n_terms = cfg->basis == SB_BASIS_STATIC ? 0 : cfg->n_terms;
+    p.M = sh.M;
+    p.inv_delta = cfg->fs / cfg->c;
+    p.t0fs = cfg->t0 * cfg->fs;
+    p.delta = (float)(cfg->c / cfg->fs);
+    p.n_sblocks = (int32_t)((sh.S + 64 * tc.nw - 1) / (64 * tc.nw));
+    p.n_scenes = batch->n_scenes;
+    int64_t items = 0;
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        Scene& s = p.scenes[i];
+        s.ball0 = batch->ball_offset[i];
+        s.n_balls = (int32_t)(batch->ball_offset[i + 1] - batch->ball_offset[i]);
+        s.frame0 = (int32_t)batch->frame_offset[i];
+        s.n_frames = (int32_t)(batch->frame_offset[i + 1] - batch->frame_offset[i]);
+        s.n_groups = (s.n_balls + tc.g - 1) / tc.g;
+        s.item0 = items;
+        items += (int64_t)s.n_frames * s.n_groups * p.n_sblocks;
+    }
+    p.n_items = items;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+    return fail(SB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace sb
+
+using namespace sb;
+
+extern "C" {
+
+int slingbag_version(void) { return (1 << 16) | 0; }
+
+const char* slingbag_last_error(void) { return g_last_error.c_str(); }
+
+int slingbag_forward(const sb_config* cfg, const sb_batch* batch, const float* balls,
+                     const float* deform, const float* frame_t, const float* sensors,
+                     float* signals, void* stream) {
+    Shape sh;
+    int st = validate_config(cfg, sh);
+    if (st) return st;
+    if ((st = validate_batch(batch, sh))) return st;
+    if (!frame_t && sh.F > 0) return fail(SB_ERR_INVALID_ARG, "frame_t is NULL");
+    if (!sensors) return fail(SB_ERR_INVALID_ARG, "sensors is NULL");
+    if (!signals && sh.F > 0) return fail(SB_ERR_INVALID_ARG, "signals is NULL");
+    if (!balls && sh.B > 0) return fail(SB_ERR_INVALID_ARG, "balls is NULL");
+    if (cfg->basis != SB_BASIS_STATIC && !deform && sh.B > 0)
+        return fail(SB_ERR_INVALID_ARG, "deform is NULL for a deformed basis");
+    DeviceState* ds;
+    if ((st = device_state(&ds))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_fill(signals, sh.F * sh.S * sh.T, 0.f, s);
+    if (e != hipSuccess) return hip_fail(e, "fill(signals)");
+    if (sh.B == 0 || sh.F == 0) return SB_OK;
+    const TileCfg tc = pick_tiles(cfg->kernel);
+    OpParams p;
+    fill_params(p, cfg, batch, sh, tc);
+    p.balls = balls;
+    p.deform = deform;
+    p.frame_t = frame_t;
+    p.sensors = sensors;
+    p.signals = signals;
+    p.flags = ds->flags;
+    e = launch_forward(p, tc, cfg->kernel, s);
+    if (e != hipSuccess) return hip_fail(e, "forward kernel");
+    return SB_OK;
+}
+
+int slingbag_loss(const sb_config* cfg, const sb_batch* batch, const float* signals,
+                  const float* measured, float* residual, double* loss, void* stream) {
+    Shape sh;
+    int st = validate_config(cfg, sh);
+    if (st) return st;
+    if ((st = validate_batch(batch, sh))) return st;
+    if (!loss) return fail(SB_ERR_INVALID_ARG, "loss is NULL");
+    const int64_t n = sh.F * sh.S * sh.T;
+    if (n > 0 && (!signals || !measured || !residual))
+        return fail(SB_ERR_INVALID_ARG, "signals / measured / residual is NULL");
+    DeviceState* ds;
+    if ((st = device_state(&ds))) return st;
+    hipError_t e = launch_loss(signals, measured, residual, n, ds->partials, loss_blocks(), loss,
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "loss kernels");
+    return SB_OK;
+}
+
+int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* balls,
+                     const float* deform, const float* frame_t, const float* sensors,
+                     const float* residual, float* grad_balls, float* grad_deform, void* stream) {
+    Shape sh;
+    int st = validate_config(cfg, sh);
+    if (st) return st;
+    if ((st = validate_batch(batch, sh))) return st;
+    if (sh.B > 0 && (!balls || !grad_balls)) return fail(SB_ERR_INVALID_ARG, "balls / grad_balls is NULL");
+    if (!sensors) return fail(SB_ERR_INVALID_ARG, "sensors is NULL");
+    if (sh.F > 0 && (!frame_t || !residual)) return fail(SB_ERR_INVALID_ARG, "frame_t / residual is NULL");
+    if (cfg->basis != SB_BASIS_STATIC && sh.B > 0 && (!deform || !grad_deform))
+        return fail(SB_ERR_INVALID_ARG, "deform / grad_deform is NULL for a deformed basis");
+    DeviceState* ds;
+    if ((st = device_state(&ds))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_fill(grad_balls, 5 * sh.B, 0.f, s);
+    if (e == hipSuccess && cfg->basis != SB_BASIS_STATIC)
+        e = launch_fill(grad_deform, 5 * (int64_t)sh.M * sh.B, 0.f, s);
+    if (e != hipSuccess) return hip_fail(e, "fill(grads)");
+    if (sh.B == 0 || sh.F == 0) return SB_OK;
+    const TileCfg tc = pick_tiles(cfg->kernel);
+    OpParams p;
+    fill_params(p, cfg, batch, sh, tc);
+    p.balls = balls;
+    p.deform = deform;
+    p.frame_t = frame_t;
+    p.sensors = sensors;
+    p.residual = residual;
+    p.grad_balls = grad_balls;
+    p.grad_deform = grad_deform;
+    p.flags = ds->flags;
+    e = launch_adjoint(p, tc, cfg->kernel, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
+    return SB_OK;
+}
+
+int slingbag_check(void* stream, uint32_t* flags) {
+    DeviceState* ds;
+    int st = device_state(&ds);
+    if (st) return st;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    unsigned f = 0;
+    e = hipMemcpy(&f, ds->flags, sizeof f, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(flags)");
+    e = hipMemset(ds->flags, 0, sizeof f);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(flags)");
+    if (flags) *flags = f;
+    if (f & (SB_FLAG_GEOMETRY | SB_FLAG_NONFINITE))
+        return fail(SB_ERR_DEVICE_FLAG, "device flags 0x%x raised (geometry=%d, nonfinite=%d)", f,
+                    (f & SB_FLAG_GEOMETRY) ? 1 : 0, (f & SB_FLAG_NONFINITE) ? 1 : 0);
+    return SB_OK;
+}
+
+}  // extern "C"

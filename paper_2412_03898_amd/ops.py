@@ -1,0 +1,94 @@
+"""Torch-facing wrappers: device tensors in, device tensors out.
+
+PyTorch supplies device memory and the current stream only; the arithmetic
+runs in libslingbag's HIP kernels through the C ABI (binding.py).  Tensors
+must be contiguous float32 on the current GPU with the layouts of
+include/slingbag.h.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import binding
+from .binding import Problem
+
+__all__ = ["Problem", "forward", "loss", "adjoint", "check", "to_device"]
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t, name, shape=None, dtype=torch.float32):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr() if t.numel() > 0 else None
+
+
+def _shapes(pb: Problem):
+    B, F = pb.n_balls, pb.n_frames
+    S, T, M = pb.cfg.n_sensors, pb.cfg.n_samples, pb.n_coef
+    return B, F, S, T, M
+
+
+def forward(pb: Problem, balls, deform, frame_t, sensors, out=None):
+    """Signals [F][S][T] of the batch (slingbag_forward)."""
+    B, F, S, T, M = _shapes(pb)
+    if out is None:
+        out = torch.empty((F, S, T), dtype=torch.float32, device=balls.device)
+    binding.forward(pb, _ptr(balls, "balls", (5, B)), _ptr(deform, "deform", (5, M, B) if M else None),
+                    _ptr(frame_t, "frame_t", (F,)), _ptr(sensors, "sensors", (3, S)),
+                    _ptr(out, "signals", (F, S, T)), _stream())
+    return out
+
+
+def loss(pb: Problem, signals, measured, residual=None, loss_out=None):
+    """(loss, residual): residual = signals - measured, loss = 1/2 sum residual^2 (device f64)."""
+    B, F, S, T, M = _shapes(pb)
+    if residual is None:
+        residual = torch.empty_like(signals)
+    if loss_out is None:
+        loss_out = torch.empty((), dtype=torch.float64, device=signals.device)
+    binding.loss(pb, _ptr(signals, "signals", (F, S, T)), _ptr(measured, "measured", (F, S, T)),
+                 _ptr(residual, "residual", (F, S, T)), _ptr(loss_out, "loss", (), torch.float64),
+                 _stream())
+    return loss_out, residual
+
+
+def adjoint(pb: Problem, balls, deform, frame_t, sensors, residual, grad_balls=None, grad_deform=None):
+    """(grad_balls [5][B], grad_deform [5][M][B] or None) given residual = dL/dsignals."""
+    B, F, S, T, M = _shapes(pb)
+    if grad_balls is None:
+        grad_balls = torch.empty((5, B), dtype=torch.float32, device=balls.device)
+    if M and grad_deform is None:
+        grad_deform = torch.empty((5, M, B), dtype=torch.float32, device=balls.device)
+    binding.adjoint(pb, _ptr(balls, "balls", (5, B)), _ptr(deform, "deform", (5, M, B) if M else None),
+                    _ptr(frame_t, "frame_t", (F,)), _ptr(sensors, "sensors", (3, S)),
+                    _ptr(residual, "residual", (F, S, T)), _ptr(grad_balls, "grad_balls", (5, B)),
+                    _ptr(grad_deform, "grad_deform", (5, M, B)) if M else None, _stream())
+    return grad_balls, (grad_deform if M else None)
+
+
+def check() -> int:
+    """Synchronise the current stream and return the device flag bits (raises on errors)."""
+    return binding.check(_stream())
+
+
+def to_device(wl, device="cuda"):
+    """Move a synthetic workload's arrays to the GPU: (Problem, balls, deform, frame_t, sensors)."""
+    pb = Problem.from_workload(wl)
+    dev = torch.device(device)
+    balls = torch.from_numpy(wl.balls).to(dev).contiguous()
+    deform = torch.from_numpy(wl.deform).to(dev).contiguous() if wl.deform is not None else None
+    frame_t = torch.from_numpy(wl.frame_t).to(dev).contiguous()
+    sensors = torch.from_numpy(wl.sensors).to(dev).contiguous()
+    return pb, balls, deform, frame_t, sensors

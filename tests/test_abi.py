@@ -1,0 +1,121 @@
+"""Host-side tests of the C ABI: the library loads, exports every declared symbol,
+and rejects invalid arguments before touching the device.
+
+Every invalid call below leaves at least one required pointer NULL or fails a
+scalar check that precedes all device work, so nothing is ever launched.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from paper_2412_03898_amd import binding
+from paper_2412_03898_amd.binding import Batch, Config
+
+LIB = binding.LIB_PATH
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libslingbag.so not built")
+
+
+def test_exports_every_header_symbol():
+    lib = binding.load()
+    names = binding.header_functions()
+    assert {"slingbag_forward", "slingbag_loss", "slingbag_adjoint"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version():
+    assert binding.version() >> 16 == 1
+
+
+def _cfg(**kw):
+    d = dict(kernel=0, basis=0, pos_mode=0, n_terms=0, n_sensors=4, n_samples=64,
+             c=1500.0, fs=40e6, t0=0.0)
+    d.update(kw)
+    return Config(**d)
+
+
+def _batch(bo=(0, 10), fo=(0, 1), n=None, reserved=0):
+    bo = np.asarray(bo, dtype=np.int64)
+    fo = np.asarray(fo, dtype=np.int64)
+    b = Batch(len(bo) - 1 if n is None else n, reserved,
+              bo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+              fo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    b._keep = (bo, fo)
+    return b
+
+
+def _fwd(cfg, batch, balls=None, deform=None, frame_t=None, sensors=None, signals=None):
+    lib = binding.load()
+    return lib.slingbag_forward(ctypes.byref(cfg) if cfg is not None else None,
+                                ctypes.byref(batch) if batch is not None else None,
+                                balls, deform, frame_t, sensors, signals, None)
+
+
+# The device pointers are left NULL: the scalar checks come first and must fail.
+@pytest.mark.parametrize("cfg_kw,code,msg", [
+    (dict(kernel=2), binding.SB_ERR_INVALID_ARG, "kernel"),
+    (dict(basis=3), binding.SB_ERR_INVALID_ARG, "basis"),
+    (dict(pos_mode=-1), binding.SB_ERR_INVALID_ARG, "pos_mode"),
+    (dict(basis=1, n_terms=0), binding.SB_ERR_SHAPE, "n_terms"),
+    (dict(basis=1, n_terms=9), binding.SB_ERR_SHAPE, "n_terms"),
+    (dict(basis=2, n_terms=17), binding.SB_ERR_SHAPE, "n_terms"),
+    (dict(n_sensors=0), binding.SB_ERR_SHAPE, "n_sensors"),
+    (dict(n_samples=0), binding.SB_ERR_SHAPE, "n_samples"),
+    (dict(n_samples=(1 << 28) + 1), binding.SB_ERR_SHAPE, "n_samples"),
+    (dict(c=float("nan")), binding.SB_ERR_NONFINITE, "finite"),
+    (dict(t0=float("inf")), binding.SB_ERR_NONFINITE, "finite"),
+    (dict(c=-1.0), binding.SB_ERR_INVALID_ARG, "> 0"),
+    (dict(fs=0.0), binding.SB_ERR_INVALID_ARG, "> 0"),
+])
+def test_config_validation(cfg_kw, code, msg):
+    assert _fwd(_cfg(**cfg_kw), _batch()) == code
+    assert msg in binding.last_error()
+
+
+@pytest.mark.parametrize("batch_kw,code,msg", [
+    (dict(bo=(0,), fo=(0,), n=0), binding.SB_ERR_SHAPE, "n_scenes"),
+    (dict(bo=tuple(range(34)), fo=tuple(range(34)), n=33), binding.SB_ERR_SHAPE, "n_scenes"),
+    (dict(reserved=1), binding.SB_ERR_INVALID_ARG, "reserved"),
+    (dict(bo=(1, 10)), binding.SB_ERR_SHAPE, "start at 0"),
+    (dict(bo=(0, 10, 5), fo=(0, 1, 2)), binding.SB_ERR_SHAPE, "decrease"),
+    (dict(fo=(0, 3, 2), bo=(0, 1, 2)), binding.SB_ERR_SHAPE, "decrease"),
+])
+def test_batch_validation(batch_kw, code, msg):
+    assert _fwd(_cfg(), _batch(**batch_kw)) == code
+    assert msg in binding.last_error()
+
+
+def test_null_structs():
+    assert _fwd(None, _batch()) == binding.SB_ERR_INVALID_ARG
+    assert _fwd(_cfg(), None) == binding.SB_ERR_INVALID_ARG
+
+
+def test_null_pointers_rejected():
+    # every required pointer NULL -> rejected before any device work
+    assert _fwd(_cfg(), _batch()) == binding.SB_ERR_INVALID_ARG
+    lib = binding.load()
+    cfg, b = _cfg(), _batch()
+    assert lib.slingbag_loss(ctypes.byref(cfg), ctypes.byref(b), None, None, None, None, None) \
+        == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_adjoint(ctypes.byref(cfg), ctypes.byref(b), None, None, None, None, None,
+                                None, None, None) == binding.SB_ERR_INVALID_ARG
+
+
+def test_last_error_is_per_call_message():
+    _fwd(_cfg(kernel=7), _batch())
+    assert "unknown kernel 7" in binding.last_error()
+    _fwd(_cfg(n_samples=-3), _batch())
+    assert "n_samples" in binding.last_error()
+
+
+def test_header_constants_match_binding():
+    text = open(binding.HEADER).read()
+    for name in ("SB_OK", "SB_ERR_INVALID_ARG", "SB_ERR_SHAPE", "SB_ERR_NONFINITE", "SB_ERR_HIP",
+                 "SB_ERR_DEVICE_FLAG", "SB_MAX_SCENES"):
+        import re
+        m = re.search(rf"#define\s+{name}\s+\(?(-?\d+)\)?", text)
+        assert m, name
+        assert int(m.group(1)) == getattr(binding, name), name

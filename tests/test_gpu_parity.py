@@ -1,0 +1,267 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: relative L2 <= 1e-5 for signals, <= 1e-4 per gradient group.  Inputs are
+seeded synthetic scenes; the 'measured' data is the oracle forward of a
+perturbed scene.  Full-size workloads are compared on a sampled subset of
+sensors (the oracle runs the same subset); smaller ones element by element.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_l2, tiny_scene, with_
+from paper_2412_03898_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SIG_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def gpu_forward(wl):
+    from paper_2412_03898_amd import ops
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    y = ops.forward(pb, balls, deform, ft, sens)
+    flags = ops.check()
+    return y.cpu().numpy().astype(np.float64), flags
+
+
+def gpu_adjoint(wl, residual):
+    import torch
+    from paper_2412_03898_amd import ops
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    res = torch.from_numpy(np.ascontiguousarray(residual.astype(np.float32))).cuda()
+    gb, gd = ops.adjoint(pb, balls, deform, ft, sens, res)
+    ops.check()
+    return gb.cpu().numpy().astype(np.float64), (None if gd is None else gd.cpu().numpy().astype(np.float64))
+
+
+def gpu_loss(wl, y, d):
+    import torch
+    from paper_2412_03898_amd import ops
+    pb = ops.Problem.from_workload(wl)
+    yt = torch.from_numpy(np.ascontiguousarray(y.astype(np.float32))).cuda()
+    dt = torch.from_numpy(np.ascontiguousarray(d.astype(np.float32))).cuda()
+    L, r = ops.loss(pb, yt, dt)
+    return float(L.item()), r.cpu().numpy().astype(np.float64)
+
+
+def grad_groups(wl, gb, gd):
+    """Named parameter groups (units differ between groups)."""
+    out = {"pos": gb[0:3], "R": gb[3], "P": gb[4]}
+    if gd is not None:
+        if wl.basis == 2:
+            for kind, name in ((0, "w"), (1, "theta"), (2, "sigma")):
+                out[f"def_pos_{name}"] = gd[0:3, kind::3]
+                out[f"def_R_{name}"] = gd[3, kind::3]
+                out[f"def_P_{name}"] = gd[4, kind::3]
+        else:
+            out["def_pos"] = gd[0:3]
+            out["def_R"] = gd[3]
+            out["def_P"] = gd[4]
+    return out
+
+
+def assert_grads(wl, got, ref, tol=GRAD_TOL):
+    g = grad_groups(wl, *got)
+    r = grad_groups(wl, *ref)
+    errs = {k: rel_l2(g[k], r[k]) for k in r}
+    _say(f"grad rel-L2 {errs}")
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+
+
+def measured_for(wl, seed=1):
+    return oracle.forward(wl, balls=synth.perturbed(wl.balls, seed)).astype(np.float32)
+
+
+# ---------------------------------------------------------------- plain single frame
+@pytest.fixture(scope="module")
+def plain():
+    return synth.workload_plain()
+
+
+@pytest.mark.parametrize("order", ["unsorted", "morton"])
+def test_forward_plain(plain, order):
+    wl = plain if order == "unsorted" else synth.apply_order(plain)
+    _say(f"forward plain {order} B={wl.n_balls} S={wl.n_sensors} T={wl.n_samples}")
+    y, flags = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"forward rel-L2 {err:.3e} flags={flags}")
+    assert flags == 0
+    assert err <= SIG_TOL
+
+
+def test_loss_and_adjoint_plain(plain):
+    wl = synth.apply_order(plain)
+    d = measured_for(wl)
+    y_ref = oracle.forward(wl)
+    L_ref, r_ref = oracle.loss(y_ref, d)
+    # loss on identical FP32 inputs
+    y32 = y_ref.astype(np.float32)
+    L_gpu, r_gpu = gpu_loss(wl, y32, d)
+    L_same, _ = oracle.loss(y32, d)
+    assert L_gpu == pytest.approx(L_same, rel=1e-6)
+    # the residual is one FP32 subtraction per element: bit-exact against numpy's
+    np.testing.assert_array_equal(r_gpu.astype(np.float32), y32 - d)
+    # adjoint only: the same FP32 residual into both
+    res32 = r_ref.astype(np.float32)
+    _say("adjoint plain (same residual)")
+    assert_grads(wl, gpu_adjoint(wl, res32), oracle.adjoint(wl, res32.astype(np.float64)))
+    # end to end: each side its own forward and residual
+    y_gpu, _ = gpu_forward(wl)
+    L_e2e, r_e2e = gpu_loss(wl, y_gpu, d)
+    assert L_e2e == pytest.approx(L_ref, rel=2e-5)
+    _say("adjoint plain (end to end)")
+    assert_grads(wl, gpu_adjoint(wl, r_e2e), oracle.adjoint(wl, r_ref))
+
+
+# ---------------------------------------------------------------- 4D and variants
+def test_4d_fourier_small():
+    wl = synth.apply_order(synth.workload_vessel_4d(n_balls=4000, n_sensors=130, n_frames=16))
+    _say(f"4d fourier B={wl.n_balls} S={wl.n_sensors} F={wl.n_frames} T={wl.n_samples}")
+    y, flags = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"forward rel-L2 {err:.3e}")
+    assert err <= SIG_TOL
+    rng = np.random.default_rng(3)
+    res = (ref - ref * (1.0 + 0.05 * rng.normal(size=ref.shape))).astype(np.float32)
+    assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+
+
+VARIANTS = [
+    dict(basis=1, pos_mode=1),
+    dict(basis=2, pos_mode=0),
+    dict(basis=2, pos_mode=1),
+    dict(kernel=1, basis=0),
+    dict(kernel=1, basis=1),
+    dict(kernel=1, basis=2, pos_mode=1),
+]
+
+
+@pytest.mark.parametrize("var", VARIANTS, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+def test_variants(var):
+    wl = tiny_scene(n_balls=700, n_sensors=69, n_frames=3, seed=61, **var)
+    wl = with_(wl, balls=wl.balls.copy())
+    order = synth.morton_order(wl.balls)
+    wl.balls = np.ascontiguousarray(wl.balls[:, order])
+    if wl.deform is not None:
+        wl.deform = np.ascontiguousarray(wl.deform[:, :, order])
+    _say(f"variant {var}")
+    y, flags = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"forward rel-L2 {err:.3e}")
+    assert err <= SIG_TOL
+    rng = np.random.default_rng(4)
+    res = rng.normal(size=ref.shape).astype(np.float32) * np.float32(np.abs(ref).max())
+    assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+
+
+# ---------------------------------------------------------------- batching and edge cases
+def test_uneven_batch_with_empty_scene():
+    a = tiny_scene(n_balls=300, n_sensors=70, n_frames=2, basis=1, seed=71)
+    b = tiny_scene(n_balls=1000, n_sensors=70, n_frames=1, basis=1, seed=72)
+    wl = with_(a, balls=np.concatenate([a.balls, b.balls], axis=1),
+               deform=np.concatenate([a.deform, b.deform], axis=2),
+               frame_t=np.concatenate([a.frame_t, np.array([0.3, 0.7, 0.9], np.float32), b.frame_t]),
+               ball_offset=np.array([0, 300, 300, 1300]), frame_offset=np.array([0, 2, 5, 6]))
+    _say("uneven batch 3 scenes (one empty)")
+    y, _ = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    assert np.abs(y[2:5]).max() == 0.0
+    assert rel_l2(y, ref) <= SIG_TOL
+    rng = np.random.default_rng(5)
+    res = rng.normal(size=ref.shape).astype(np.float32)
+    assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+
+
+def test_single_ball_single_sensor():
+    wl = tiny_scene(n_balls=1, n_sensors=1, seed=81)
+    y, _ = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    assert rel_l2(y, ref) <= SIG_TOL
+    assert abs(y.sum()) < 1e-6 * np.abs(y).max()
+
+
+def test_clipped_record_is_dropped_and_flagged():
+    wl = tiny_scene(n_balls=50, n_sensors=10, seed=82)
+    wl = with_(wl, n_samples=200, t0=wl.t0 + 150 / wl.fs)   # record too short: most traces clipped
+    y, flags = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    assert flags & 4
+    assert rel_l2(y, ref) <= SIG_TOL
+
+
+def test_sensor_inside_ball_raises_flag():
+    from paper_2412_03898_amd import binding
+    wl = tiny_scene(n_balls=5, n_sensors=3, seed=83)
+    sens = wl.sensors.copy()
+    sens[:, 1] = wl.balls[0:3, 2]     # sensor 1 sits at the centre of ball 2
+    wl = with_(wl, sensors=sens)
+    with pytest.raises(binding.SlingbagError) as ei:
+        gpu_forward(wl)
+    assert ei.value.status == binding.SB_ERR_DEVICE_FLAG
+
+
+def test_nonfinite_ball_is_skipped_and_flagged():
+    from paper_2412_03898_amd import binding
+    wl = tiny_scene(n_balls=20, n_sensors=8, seed=84)
+    bad = wl.balls.copy()
+    bad[3, 7] = np.nan
+    with pytest.raises(binding.SlingbagError):
+        gpu_forward(with_(wl, balls=bad))
+    # the remaining balls still produced the right signal
+    from paper_2412_03898_amd import ops
+    import torch
+    pb, balls, deform, ft, sens = ops.to_device(with_(wl, balls=bad))
+    y = ops.forward(pb, balls, deform, ft, sens)
+    torch.cuda.synchronize()
+    try:
+        ops.check()
+    except binding.SlingbagError:
+        pass
+    keep = np.r_[0:7, 8:20]
+    ref = oracle.forward(with_(wl, balls=wl.balls[:, keep], ball_offset=np.array([0, 19])))
+    assert rel_l2(y.cpu().numpy(), ref) <= SIG_TOL
+
+
+# ---------------------------------------------------------------- full sizes, sampled sensors
+def test_vessel_static_full_size_sampled():
+    wl = synth.apply_order(synth.workload_vessel_static())
+    _say(f"vessel static full B={wl.n_balls} S={wl.n_sensors} T={wl.n_samples}")
+    y, flags = gpu_forward(wl)
+    assert flags == 0
+    sub = with_(wl, sensors=wl.sensors[:, ::16].copy())
+    ref = oracle.forward(sub)
+    err = rel_l2(y[:, ::16], ref)
+    _say(f"forward sampled rel-L2 {err:.3e}")
+    assert err <= SIG_TOL
+    rng = np.random.default_rng(6)
+    res = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
+    assert_grads(sub, gpu_adjoint(sub, res), oracle.adjoint(sub, res.astype(np.float64)))
+
+
+def test_vessel_4d_full_size_sampled():
+    wl = synth.apply_order(synth.workload_vessel_4d())
+    _say(f"vessel 4d full B={wl.n_balls} S={wl.n_sensors} F={wl.n_frames} T={wl.n_samples}")
+    y, flags = gpu_forward(wl)
+    assert flags == 0
+    sub = with_(wl, sensors=wl.sensors[:, ::16].copy())
+    ref = oracle.forward(sub)
+    err = rel_l2(y[:, ::16], ref)
+    _say(f"forward sampled rel-L2 {err:.3e}")
+    assert err <= SIG_TOL
+    rng = np.random.default_rng(7)
+    res = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
+    assert_grads(sub, gpu_adjoint(sub, res), oracle.adjoint(sub, res.astype(np.float64)))

@@ -145,10 +145,32 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch,
                      const float* sensors, const float* residual,
                      float* grad_balls, float* grad_deform, void* stream);
 
+/* One Adam step of the iterative reconstruction (Sec. 3.2 updates each
+ * parameter group - coordinates, peak pressure, size, deformation
+ * coefficients - with its own learning rate; the optimiser is not named, Adam
+ * is used).  For i < n, with g = grad[i] and t = step >= 1:
+ *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
+ *   param -= lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * param, m, v are updated in place (DEVICE, n floats each).  Call once per
+ * parameter group.  0 <= beta < 1, eps > 0. */
+int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n,
+                  float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
 /* Waits for `stream`, returns the device flag bits raised since the last
  * check in *flags (HOST, may be NULL) and clears them.  Returns
  * SB_ERR_DEVICE_FLAG if SB_FLAG_GEOMETRY or SB_FLAG_NONFINITE was raised. */
 int slingbag_check(void* stream, uint32_t* flags);
+
+/* Opt-in timing of the main kernels with HIP events recorded on each call's
+ * own stream around the kernel launch (not around the output clearing).
+ * slingbag_timing(1) creates the events on the current device and starts
+ * recording; slingbag_timing(0) stops.  slingbag_timing_read waits for the
+ * recorded events and returns, per kind [forward, adjoint, loss, adam], the
+ * summed kernel milliseconds in total_ms[4] and the launch count in
+ * launches[4] (HOST arrays), then resets the counters.  At most 8192 launches
+ * per kind are recorded between reads.  Not for use under graph capture. */
+int slingbag_timing(int enable);
+int slingbag_timing_read(double* total_ms, int64_t* launches);
 
 /* Message for the last non-OK status returned on the calling host thread. */
 const char* slingbag_last_error(void);

@@ -181,3 +181,15 @@ def deformed(wl, frame: int, balls=None, deform=None) -> np.ndarray:
                           _ptr(balls), _ptr(dfm), _ptr(_f64(wl.frame_t)), int(frame), _ptr(out))
     _check(st, "oracle deformed")
     return out
+
+
+def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One bias-corrected Adam step in float64 (new param, m, v): the textbook update
+    m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, p -= lr mhat / (sqrt(vhat) + eps)."""
+    p = np.asarray(param, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

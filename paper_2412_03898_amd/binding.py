@@ -59,6 +59,10 @@ _SIGS = {
     "slingbag_adjoint": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP,
                          _VP, _VP, _VP],
     "slingbag_check": [_VP, ctypes.POINTER(ctypes.c_uint32)],
+    "slingbag_adam": [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP],
+    "slingbag_timing": [ctypes.c_int],
+    "slingbag_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     "slingbag_last_error": [],
     "slingbag_version": [],
 }
@@ -156,6 +160,11 @@ def adjoint(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, re
                                    frame_t, sensors, residual, grad_balls, grad_deform, stream))
 
 
+def adam(param: int, grad: int, m: int, v: int, n: int, lr: float, beta1: float, beta2: float,
+         eps: float, step: int, stream: int = 0):
+    _check(load().slingbag_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, stream))
+
+
 def check(stream: int = 0) -> int:
     """Wait for the stream; return the device flag bits (raises on geometry/non-finite flags)."""
     flags = ctypes.c_uint32(0)
@@ -163,6 +172,21 @@ def check(stream: int = 0) -> int:
     if st != SB_OK:
         raise SlingbagError(st, last_error())
     return int(flags.value)
+
+
+def timing(enable: bool):
+    _check(load().slingbag_timing(1 if enable else 0))
+
+
+TIMING_KINDS = ("forward", "adjoint", "loss", "adam")
+
+
+def timing_read() -> dict:
+    """{kind: (total_ms, launches)} of the main kernels since the last read."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    _check(load().slingbag_timing_read(ms, n))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMING_KINDS)}
 
 
 def version() -> int:

@@ -152,6 +152,28 @@ static int hip_fail(hipError_t e, const char* what) {
     return fail(SB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Opt-in event timing of the main kernel launches (slingbag_timing).  Each
+// launch of kind k is bracketed by two events recorded on its own stream; the
+// pool holds kTimingSlots pairs per kind and recording stops when it is full.
+enum { kTimeForward = 0, kTimeAdjoint = 1, kTimeLoss = 2, kTimeAdam = 3, kTimeKinds = 4 };
+constexpr int kTimingSlots = 8192;
+struct Timing {
+    bool enabled = false;
+    int device = -1;
+    std::vector<hipEvent_t> ev[kTimeKinds];   // 2 per slot
+    int used[kTimeKinds] = {0, 0, 0, 0};
+};
+static Timing g_timing;
+
+static void time_mark(int kind, int which, hipStream_t st) {
+    if (!g_timing.enabled) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int slot = g_timing.used[kind];
+    if (slot >= kTimingSlots) return;
+    hipEventRecord(g_timing.ev[kind][2 * slot + which], st);
+    if (which == 1) g_timing.used[kind] = slot + 1;
+}
+
 }  // namespace sb
 
 using namespace sb;
@@ -190,7 +212,9 @@ int slingbag_forward(const sb_config* cfg, const sb_batch* batch, const float* b
     p.sensors = sensors;
     p.signals = signals;
     p.flags = ds->flags;
+    time_mark(kTimeForward, 0, s);
     e = launch_forward(p, tc, cfg->kernel, s);
+    time_mark(kTimeForward, 1, s);
     if (e != hipSuccess) return hip_fail(e, "forward kernel");
     return SB_OK;
 }
@@ -207,8 +231,10 @@ int slingbag_loss(const sb_config* cfg, const sb_batch* batch, const float* sign
         return fail(SB_ERR_INVALID_ARG, "signals / measured / residual is NULL");
     DeviceState* ds;
     if ((st = device_state(&ds))) return st;
+    time_mark(kTimeLoss, 0, (hipStream_t)stream);
     hipError_t e = launch_loss(signals, measured, residual, n, ds->partials, loss_blocks(), loss,
                                (hipStream_t)stream);
+    time_mark(kTimeLoss, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "loss kernels");
     return SB_OK;
 }
@@ -244,8 +270,67 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* b
     p.grad_balls = grad_balls;
     p.grad_deform = grad_deform;
     p.flags = ds->flags;
+    time_mark(kTimeAdjoint, 0, s);
     e = launch_adjoint(p, tc, cfg->kernel, s);
+    time_mark(kTimeAdjoint, 1, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
+    return SB_OK;
+}
+
+int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                  float beta1, float beta2, float eps, int32_t step, void* stream) {
+    if (n < 0) return fail(SB_ERR_SHAPE, "n must be >= 0");
+    if (n > 0 && (!param || !grad || !m || !v)) return fail(SB_ERR_INVALID_ARG, "NULL Adam buffer");
+    if (step < 1) return fail(SB_ERR_INVALID_ARG, "step must be >= 1 (got %d)", step);
+    if (!isfinite(lr) || !isfinite(eps) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+        return fail(SB_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    time_mark(kTimeAdam, 0, (hipStream_t)stream);
+    hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    time_mark(kTimeAdam, 1, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adam kernel");
+    return SB_OK;
+}
+
+int slingbag_timing(int enable) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (enable && g_timing.device != dev) {
+        for (int k = 0; k < kTimeKinds; ++k) {
+            for (hipEvent_t ev : g_timing.ev[k]) hipEventDestroy(ev);
+            g_timing.ev[k].assign(2 * kTimingSlots, nullptr);
+            for (auto& ev : g_timing.ev[k]) {
+                e = hipEventCreate(&ev);
+                if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+            }
+            g_timing.used[k] = 0;
+        }
+        g_timing.device = dev;
+    }
+    g_timing.enabled = enable != 0;
+    return SB_OK;
+}
+
+int slingbag_timing_read(double* total_ms, int64_t* launches) {
+    if (!total_ms || !launches) return fail(SB_ERR_INVALID_ARG, "NULL output");
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int k = 0; k < kTimeKinds; ++k) {
+        double sum = 0.0;
+        const int n = g_timing.device >= 0 ? g_timing.used[k] : 0;
+        for (int i = 0; i < n; ++i) {
+            hipError_t e = hipEventSynchronize(g_timing.ev[k][2 * i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, g_timing.ev[k][2 * i], g_timing.ev[k][2 * i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            sum += ms;
+        }
+        total_ms[k] = sum;
+        launches[k] = n;
+        if (g_timing.device >= 0) g_timing.used[k] = 0;
+    }
     return SB_OK;
 }
 

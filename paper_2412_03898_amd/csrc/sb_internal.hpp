@@ -250,5 +250,7 @@ hipError_t launch_fill(float* ptr, int64_t n, float v, hipStream_t st);
 hipError_t launch_loss(const float* y, const float* d, float* r, int64_t n, double* partials,
                        int n_blocks, double* loss, hipStream_t st);
 int loss_blocks();
+hipError_t launch_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t st);
 
 }  // namespace sb

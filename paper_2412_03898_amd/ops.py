@@ -13,7 +13,7 @@ import torch
 from . import binding
 from .binding import Problem
 
-__all__ = ["Problem", "forward", "loss", "adjoint", "check", "to_device"]
+__all__ = ["Problem", "forward", "loss", "adjoint", "adam_", "check", "to_device"]
 
 
 def _stream() -> int:
@@ -76,6 +76,17 @@ def adjoint(pb: Problem, balls, deform, frame_t, sensors, residual, grad_balls=N
                     _ptr(residual, "residual", (F, S, T)), _ptr(grad_balls, "grad_balls", (5, B)),
                     _ptr(grad_deform, "grad_deform", (5, M, B)) if M else None, _stream())
     return grad_balls, (grad_deform if M else None)
+
+
+def adam_(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on one parameter group (slingbag_adam); tensors of equal size."""
+    n = param.numel()
+    for t, name in ((grad, "grad"), (m, "m"), (v, "v")):
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    binding.adam(_ptr(param, "param"), _ptr(grad, "grad"), _ptr(m, "m"), _ptr(v, "v"), n,
+                 float(lr), float(beta1), float(beta2), float(eps), int(step), _stream())
+    return param
 
 
 def check() -> int:

@@ -367,3 +367,18 @@ def test_oracle_regression_fixture():
     assert set(got) == set(stored)
     for key, val in stored.items():
         assert got[key] == pytest.approx(val, rel=1e-12), key
+
+
+def test_adam_first_step_is_signed_lr():
+    """With zero moments, the first bias-corrected Adam step moves each parameter by
+    lr * g/(|g| + eps): lr*sign(g) for |g| >> eps."""
+    rng = np.random.default_rng(9)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50) * 10.0
+    newp, m, v = oracle.adam_step(p, g, np.zeros(50), np.zeros(50), lr=1e-3, step=1)
+    np.testing.assert_allclose(newp, p - 1e-3 * np.sign(g), rtol=0, atol=1e-3 * 1e-8 / 1e-2 + 1e-15)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+    # a constant gradient keeps the step at lr (bias correction cancels the moment decay)
+    p2, m2, v2 = oracle.adam_step(newp, g, m, v, lr=1e-3, step=2)
+    np.testing.assert_allclose(p2, newp - 1e-3 * np.sign(g), atol=1e-12)

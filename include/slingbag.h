@@ -145,6 +145,25 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch,
                      const float* sensors, const float* residual,
                      float* grad_balls, float* grad_deform, void* stream);
 
+/* Ball order (performance only: every result is independent of the order of
+ * the balls within a scene).  Writes perm (DEVICE int32 [B_total]) such that
+ * placing ball perm[i] at position i sorts every scene's balls along the
+ * Morton (Z-order) curve of a fixed grid (2^-18 m cells over [-1 m, 1 m)^3,
+ * positions outside are clamped to its faces); perm stays within each
+ * scene's range and is stable for equal keys.  Ordered balls let the forward
+ * group neighbours into short arrival windows and the adjoint stage compact
+ * residual rows.  Apply perm to every per-ball array (balls, deform,
+ * optimiser state) with slingbag_permute.  Scratch: a per-device buffer
+ * (keys, indices and radix-sort storage, about 24 bytes per ball), allocated
+ * on first use and grown as needed.  B_total must be below 2^31. */
+int slingbag_order(const sb_batch* batch, const float* balls, int32_t* perm, void* stream);
+
+/* dst[r][i] = src[r][perm[i]] for r < rows, i < n (DEVICE float arrays of
+ * rows*n elements, DEVICE int32 perm of n entries in [0, n)); dst must not
+ * alias src. */
+int slingbag_permute(const float* src, float* dst, int64_t rows, int64_t n, const int32_t* perm,
+                     void* stream);
+
 /* One Adam step of the iterative reconstruction (Sec. 3.2 updates each
  * parameter group - coordinates, peak pressure, size, deformation
  * coefficients - with its own learning rate; the optimiser is not named, Adam

@@ -61,6 +61,8 @@ _SIGS = {
     "slingbag_check": [_VP, ctypes.POINTER(ctypes.c_uint32)],
     "slingbag_adam": [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP],
+    "slingbag_order": [ctypes.POINTER(Batch), _VP, _VP, _VP],
+    "slingbag_permute": [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP],
     "slingbag_timing": [ctypes.c_int],
     "slingbag_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     "slingbag_last_error": [],
@@ -163,6 +165,14 @@ def adjoint(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, re
 def adam(param: int, grad: int, m: int, v: int, n: int, lr: float, beta1: float, beta2: float,
          eps: float, step: int, stream: int = 0):
     _check(load().slingbag_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, stream))
+
+
+def order(pb: Problem, balls: int, perm: int, stream: int = 0):
+    _check(load().slingbag_order(ctypes.byref(pb.batch), balls, perm, stream))
+
+
+def permute(src: int, dst: int, rows: int, n: int, perm: int, stream: int = 0):
+    _check(load().slingbag_permute(src, dst, rows, n, perm, stream))
 
 
 def check(stream: int = 0) -> int:

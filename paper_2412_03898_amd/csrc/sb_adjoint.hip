@@ -1,204 +1,277 @@
 // Adjoint: gradient of 1/2 |y - d|^2 with respect to every ball attribute and
 // deformation coefficient, given the residual y - d.
 //
-// Same work items and staging as the forward.  Each lane loads its sensor's
-// residual samples [o, o + UCAP) into its LDS column, then for each
-// wave-uniform ball gathers the residual over the ball's window and forms the
-// derivative of the sampled trace with respect to the arrival time, the size
-// and the pressure (summation by parts over the window boundaries, so each
-// boundary is evaluated once).  The 64 lanes' contributions are reduced across
-// the wave into per-ball accumulators in LDS; after the group, one thread per
-// ball applies the chain rule through Eq. 1 (and Eq. 2 / the Fourier series)
-// and adds the result to the global gradients.
+// Work item = (scene, chunk of 256 consecutive balls, split of the sensors).
+// A block of four waves takes the chunk and ranks its balls by size, so that
+// each wave holds 64 balls of similar size (similar window lengths keep the
+// lanes of a wave busy for the same number of samples); lane = ball.  For
+// every frame of the scene the lane deforms its ball (Eq. 1, recomputed here),
+// and for every sensor of the split the wave stages the residual samples around
+// its balls' arrival times in an LDS row (64 consecutive samples per coalesced
+// load; the next sensor's row is fetched while the current one is used).  Each
+// lane gathers its window from the row and accumulates the five derivatives of
+// the loss with respect to its deformed ball in registers: no cross-lane
+// reductions and no atomics until the chain rule at the end of the item.
 //
-// With dr_m = r_m - r_{m-1} (residual samples of the window, r_{-1} = r_W = 0)
-// and in_m = [|x_m| < rho] decided in FP64:
-//   uniform:  G_v = C sum Q_m dr_m,  G_tau = 2C sum in_m x_m dr_m,
-//             G_rho = -2 rho C sum in_m dr_m
-//   gaussian: G_v = -K S0,  G_tau = K/rho^2 S1,  G_rho = -2K/rho S0 - K/rho^3 S2,
-//             S_n = sum x_m^n E_m dr_m
-// and dL/dr = G_tau/delta - G_v/r, dL/dR_f = G_rho/delta, dL/dP_f = G_v/P_f,
-// dL/dx_f = dL/dr (x_f - s)/r.
+// Sums by parts over the window boundaries x_m (residual differences
+// dr_m = r_m - r_{m-1}, r_{-1} = r_W = 0).  Uniform sphere: boundaries m = 1..m_hi
+// lie strictly inside (-rho, rho) (decided in FP64); the clamped ones
+// telescope, so with
+//   S_w = sum_in x_m^2 dr_m - rho^2 S_r,  S_t = sum_in x_m dr_m,  S_r = r_{m_hi} - r_0
+// and C = P_f delta / (4r):  G_v = C S_w,  G_tau = 2 C S_t,  G_rho = -2 rho C S_r.
+// Gaussian ball: all boundaries, E_m = exp(-x_m^2 / (2 rho^2)), K = P_f rho^2 delta/(2r),
+// S_n = sum x_m^n E_m dr_m:  G_v = -K S0,  G_tau = K/rho^2 S1,
+// G_rho = -2K/rho S0 - K/rho^3 S2.
+// Then dL/dr = G_tau/delta - G_v/r, dL/dR_f = G_rho/delta, dL/dP_f = G_v/P_f and
+// dL/dx_f = dL/dr (x_f - s)/r; the chain rule through Eq. 1 (and Eq. 2 or the
+// Fourier series) gives the parameter gradients.
 
 #include "sb_internal.hpp"
 
 namespace sb {
 
-__device__ inline float wave_sum(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+constexpr int kAdjChunk = 256;   // balls per block item (4 waves x 64 lanes)
+
+// Per-lane gather of one pair's window from a row reader rd(m) = residual at
+// sample k_lo + m.  Returns the three sums of the uniform sphere (Sw, St, Sr) or
+// of the Gaussian ball (S0, S1, S2).
+template <int KERNEL, typename Reader>
+__device__ inline void gather_window(const PairWin<KERNEL>& w, float rho, Reader rd, float& A,
+                                     float& Bs, float& Cs) {
+    float x = (float)w.a0;
+    if (KERNEL == SB_KERNEL_UNIFORM) {
+        const float r0 = rd(0);
+        float rp = r0, sw = 0.f, st = 0.f;
+        for (int m = 1; m <= w.m_hi; ++m) {
+            x -= 1.f;
+            const float rm = rd(m);
+            const float dr = rm - rp;
+            rp = rm;
+            sw = fmaf(x * x, dr, sw);
+            st = fmaf(x, dr, st);
+        }
+        const float sr = rp - r0;
+        A = fmaf(-rho * rho, sr, sw);
+        Bs = st;
+        Cs = sr;
+    } else {
+        const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale
+        float rp = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int m = 0; m <= w.W; ++m) {
+            const float rm = (m < w.W) ? rd(m) : 0.f;
+            const float dr = rm - rp;
+            rp = rm;
+            const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
+            s0 += e;
+            s1 = fmaf(x, e, s1);
+            s2 = fmaf(x * x, e, s2);
+            x -= 1.f;
+        }
+        A = s0;
+        Bs = s1;
+        Cs = s2;
+    }
 }
 
-template <int NW, int G, int UCAP, int KERNEL>
-__global__ __launch_bounds__(64 * NW) void adjoint_kernel(OpParams p) {
-    __shared__ BallF sball[G];
-    __shared__ float tile[NW][UCAP][64];
-    __shared__ float acc[G][5];
-    __shared__ double sred[NW * 6];
-    __shared__ double scen[3];
+template <int UROW, int KERNEL, int MREG>
+__global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
+    static_assert(UROW % 64 == 0, "row length must be a multiple of 64");
+    constexpr int NQ = UROW / 64;
+    __shared__ float rowbuf[4][UROW];
+    __shared__ float sR[kAdjChunk];
+    __shared__ int sperm[kAdjChunk];
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    float* col = &tile[wid][0][lane];
+    float* const row = rowbuf[wid];
+    const float delta = p.delta;
+    const float inv_delta_f = (float)p.inv_delta;
 
     for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
-        const Item it = decode_item(p, item);
+        const ItemA it = decode_item_adj(p, item);
         const Scene& sc = p.scenes[it.scene];
-        const int gf = sc.frame0 + it.frame;
-        const float t = p.frame_t[gf];
-        __syncthreads();   // previous item's chain-rule readers of acc/sball are done
-        for (int i = tid; i < G * 5; i += 64 * NW) (&acc[0][0])[i] = 0.f;
-        int nb;
-        stage_group<NW, G>(p, sc, it.group, t, sball, sred, scen, nb);
+        const int nb = min(kAdjChunk, sc.n_balls - it.chunk * kAdjChunk);
+        const int64_t first = sc.ball0 + (int64_t)it.chunk * kAdjChunk;
+        const int s_begin = it.split * p.s_per_split;
+        const int s_end = min(p.S, s_begin + p.s_per_split);
 
-        const int s = it.sblock * 64 * NW + wid * 64 + lane;
-        const bool active = s < p.S;
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
-        const int o = tile_origin(p, scen, sx, sy, sz, UCAP);
-        const float* res_row = p.residual + ((int64_t)gf * p.S + (active ? s : 0)) * p.T;
-        for (int k = 0; k < UCAP; ++k) {
-            const int kg = o + k;
-            col[k * 64] = (active && kg >= 0 && kg < p.T) ? res_row[kg] : 0.f;
+        // ---- rank the chunk's balls by base size; wave w takes ranks 64w..64w+63
+        __syncthreads();
+        const float Ri = tid < nb ? p.balls[3 * p.B + first + tid] : 3.0e38f;
+        sR[tid] = Ri;
+        __syncthreads();
+        int rank = 0;
+        for (int j = 0; j < kAdjChunk; ++j) {
+            const float Rj = sR[j];
+            rank += (Rj < Ri) || (Rj == Ri && j < tid);
         }
+        sperm[rank] = tid;
+        __syncthreads();
+        const int li = sperm[wid * 64 + lane];
+        const bool valid = li < nb;
+        const int64_t b = first + (valid ? li : 0);
 
-        for (int bi = 0; bi < nb; ++bi) {
-            const BallF bl = sball[bi];
-            if (bl.rho < 0.0) continue;
-            float gx = 0.f, gy = 0.f, gz = 0.f, gR = 0.f, gP = 0.f;
-            if (active) {
+        float gb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float gd[5][MREG > 0 ? MREG : 1];
+        for (int a = 0; a < 5; ++a)
+            for (int m = 0; m < (MREG > 0 ? MREG : 1); ++m) gd[a][m] = 0.f;
+
+        for (int f = 0; f < sc.n_frames; ++f) {
+            const int gf = sc.frame0 + f;
+            const float t = p.frame_t[gf];
+            BallF bl;
+            bool live = false;
+            if (valid) {
+                double fb[2 * SB_MAX_FOURIER];
+                if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
+                live = deform_ball(p, b, t, fb, bl);
+                if (!live) raise_flag(p.flags, SB_FLAG_NONFINITE);
+            }
+            // bounding box (rounded outwards) and largest size of the wave's live balls
+            float lo[3], hi[3];
+            lo[0] = live ? __double2float_rd(bl.x) : 3.0e38f;
+            lo[1] = live ? __double2float_rd(bl.y) : 3.0e38f;
+            lo[2] = live ? __double2float_rd(bl.z) : 3.0e38f;
+            hi[0] = live ? __double2float_ru(bl.x) : -3.0e38f;
+            hi[1] = live ? __double2float_ru(bl.y) : -3.0e38f;
+            hi[2] = live ? __double2float_ru(bl.z) : -3.0e38f;
+            float rmax = live ? bl.rhof : 0.f;
+            for (int a = 0; a < 3; ++a) { lo[a] = wave_min(lo[a]); hi[a] = wave_max(hi[a]); }
+            rmax = wave_max(rmax);
+            if (!(lo[0] <= hi[0])) continue;           // no live ball in this wave
+            const double hmax = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rmax : (double)kGaussCut * rmax;
+
+            const float* res_frame = p.residual + (int64_t)gf * p.S * p.T;
+            float g5[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+
+            // row origin of a sensor: every window of the wave starts at or after o + 1
+            auto origin = [&](int s) -> int {
+                double dmin, dmax;
+                box_distance_range(lo, hi, (double)p.sensors[s], (double)p.sensors[p.S + s],
+                                   (double)p.sensors[2 * p.S + s], dmin, dmax);
+                const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
+                return (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
+            };
+            float pf[NQ];
+            int o_next = 0;
+            if (s_begin < s_end) {
+                o_next = origin(s_begin);
+                const float* rr = res_frame + (int64_t)s_begin * p.T;
+                for (int q = 0; q < NQ; ++q) {
+                    const int k = o_next + q * 64 + lane;
+                    pf[q] = (k >= 0 && k < p.T) ? rr[k] : 0.f;
+                }
+            }
+            for (int s = s_begin; s < s_end; ++s) {
+                const int o = o_next;
+                wave_lds_sync();
+                for (int q = 0; q < NQ; ++q) row[q * 64 + lane] = pf[q];
+                wave_lds_sync();
+                if (s + 1 < s_end) {            // fetch the next sensor's row
+                    o_next = origin(s + 1);
+                    const float* rr = res_frame + (int64_t)(s + 1) * p.T;
+                    for (int q = 0; q < NQ; ++q) {
+                        const int k = o_next + q * 64 + lane;
+                        pf[q] = (k >= 0 && k < p.T) ? rr[k] : 0.f;
+                    }
+                }
+                if (!live) continue;
+                const double sx = p.sensors[s], sy = p.sensors[p.S + s], sz = p.sensors[2 * p.S + s];
                 const double dx = bl.x - sx, dy = bl.y - sy, dz = bl.z - sz;
-                const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl, dx, dy, dz);
+                const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, dx, dy, dz);
                 if (!w.ok) {
                     raise_flag(p.flags, SB_FLAG_GEOMETRY);
-                } else if (w.in_range) {   // otherwise the window reads only zeros
-                    const float rho = bl.rhof;
-                    const int W = w.W;
-                    const int tl = w.klo - o;
-                    const bool in_tile = tl >= 0 && tl + W <= UCAP;
-                    const float* c = col + (in_tile ? tl : 0) * 64;
-                    float x = (float)w.a0;
-                    float rp = 0.f;
-                    float dLdr, dLdR, dLdP;
-                    const float rf = (float)w.r;
-                    if (KERNEL == SB_KERNEL_UNIFORM) {
-                        // boundaries m_lo..m_hi lie strictly inside (-rho, rho)
-                        const int m_lo = (int)floor(w.a0 - bl.rho) + 1;
-                        const int m_hi = (int)ceil(w.a0 + bl.rho) - 1;
-                        float Sw = 0.f, St = 0.f, Sr = 0.f;
-                        for (int m = 0; m <= W; ++m) {
-                            float rm = 0.f;
-                            if (m < W) {
-                                if (in_tile) rm = c[m * 64];
-                                else {
-                                    const int kg = w.klo + m;
-                                    rm = (kg >= 0 && kg < p.T) ? res_row[kg] : 0.f;
-                                }
-                            }
-                            const float dr = rm - rp;
-                            rp = rm;
-                            const bool in = (m >= m_lo) && (m <= m_hi);
-                            const float q = in ? x : (m < m_lo ? rho : -rho);
-                            Sw = fmaf(q * q, dr, Sw);
-                            St = fmaf(in ? x : 0.f, dr, St);
-                            Sr += in ? dr : 0.f;
-                            x -= 1.f;
-                        }
-                        const float C = (float)((double)bl.amp * (double)p.delta / (4.0 * w.r));
-                        const float Gv = C * Sw, Gt = 2.f * C * St, Gr = -2.f * rho * C * Sr;
-                        dLdr = Gt / p.delta - Gv / rf;
-                        dLdR = Gr / p.delta;
-                        dLdP = (p.delta / (4.f * rf)) * Sw;
-                    } else {
-                        float S0 = 0.f, S1 = 0.f, S2 = 0.f;
-                        const float ce = -1.f / (2.f * rho * rho);
-                        for (int m = 0; m <= W; ++m) {
-                            float rm = 0.f;
-                            if (m < W) {
-                                if (in_tile) rm = c[m * 64];
-                                else {
-                                    const int kg = w.klo + m;
-                                    rm = (kg >= 0 && kg < p.T) ? res_row[kg] : 0.f;
-                                }
-                            }
-                            const float dr = rm - rp;
-                            rp = rm;
-                            const float E = expf(x * x * ce) * dr;
-                            S0 += E;
-                            S1 = fmaf(x, E, S1);
-                            S2 = fmaf(x * x, E, S2);
-                            x -= 1.f;
-                        }
-                        const float Kr = rho * rho * p.delta / (2.f * rf);   // K / P_f
-                        const float K = bl.amp * Kr;
-                        const float Gv = -K * S0;
-                        const float Gt = K / (rho * rho) * S1;
-                        const float Ga = -2.f * K / rho * S0 - K / (rho * rho * rho) * S2;
-                        dLdr = Gt / p.delta - Gv / rf;
-                        dLdR = Ga / p.delta;
-                        dLdP = -Kr * S0;
-                    }
-                    gx = dLdr * (float)(dx / w.r);
-                    gy = dLdr * (float)(dy / w.r);
-                    gz = dLdr * (float)(dz / w.r);
-                    gR = dLdR;
-                    gP = dLdP;
+                    continue;
                 }
+                if (!w.in_range) continue;      // the window reads only zeros
+                const float rho = bl.rhof;
+                const int tl = w.klo - o;
+                float A, Bs, Cs;
+                if (tl >= 0 && tl + w.W <= UROW) {
+                    const float* rw = row + tl;
+                    gather_window<KERNEL>(w, rho, [&](int m) { return rw[m]; }, A, Bs, Cs);
+                } else {
+                    const float* rr = res_frame + (int64_t)s * p.T;
+                    const int klo = w.klo, T = p.T;
+                    gather_window<KERNEL>(
+                        w, rho, [&](int m) { const int k = klo + m; return (k >= 0 && k < T) ? rr[k] : 0.f; },
+                        A, Bs, Cs);
+                }
+                const float rf = (float)w.r;
+                const float inv_r = __builtin_amdgcn_rcpf(rf);
+                float dLdr, dLdR, dLdP;
+                if (KERNEL == SB_KERNEL_UNIFORM) {
+                    const float Cr = delta * 0.25f * inv_r;   // C / P_f
+                    const float C = bl.amp * Cr;
+                    const float Gv = C * A, Gt = 2.f * C * Bs, Gr = -2.f * rho * C * Cs;
+                    dLdr = Gt * inv_delta_f - Gv * inv_r;
+                    dLdR = Gr * inv_delta_f;
+                    dLdP = Cr * A;
+                } else {
+                    const float Kr = rho * rho * delta * 0.5f * inv_r;   // K / P_f
+                    const float K = bl.amp * Kr;
+                    const float Gv = -K * A;
+                    const float Gt = K / (rho * rho) * Bs;
+                    const float Ga = -2.f * K / rho * A - K / (rho * rho * rho) * Cs;
+                    dLdr = Gt * inv_delta_f - Gv * inv_r;
+                    dLdR = Ga * inv_delta_f;
+                    dLdP = -Kr * A;
+                }
+                g5[0] = fmaf(dLdr, (float)dx * inv_r, g5[0]);
+                g5[1] = fmaf(dLdr, (float)dy * inv_r, g5[1]);
+                g5[2] = fmaf(dLdr, (float)dz * inv_r, g5[2]);
+                g5[3] += dLdR;
+                g5[4] += dLdP;
             }
-            gx = wave_sum(gx);
-            gy = wave_sum(gy);
-            gz = wave_sum(gz);
-            gR = wave_sum(gR);
-            gP = wave_sum(gP);
-            if (lane < 5) {
-                const float v = lane == 0 ? gx : lane == 1 ? gy : lane == 2 ? gz : lane == 3 ? gR : gP;
-                atomicAdd(&acc[bi][lane], v);
+            // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame
+            if (live) {
+                double fb[2 * SB_MAX_FOURIER];
+                if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
+                float base[5];
+                for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
+                for (int a = 0; a < 5; ++a) {
+                    const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
+                    const float h = (float)eval_H(p, b, a, t, fb);
+                    gb[a] += additive ? g5[a] : g5[a] * (1.f + h);
+                    const float gs = additive ? g5[a] : g5[a] * base[a];
+                    if (MREG > 0) {
+                        for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)fb[m], gd[a][m]);
+                    } else if (p.basis != SB_BASIS_STATIC) {
+                        for (int m = 0; m < p.M; ++m)
+                            unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b,
+                                            gs * eval_dH(p, b, a, m, t, fb));
+                    }
+                }
             }
         }
-        __syncthreads();
-
-        // chain rule through Eq. 1 (and Eq. 2 / Fourier) for this frame
-        double fb[2 * SB_MAX_FOURIER];
-        if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
-        const int64_t first = sc.ball0 + (int64_t)it.group * G;
-        for (int i = tid; i < nb; i += 64 * NW) {
-            if (sball[i].rho < 0.0) continue;
-            const int64_t b = first + i;
+        if (valid) {
             for (int a = 0; a < 5; ++a) {
-                const float g = acc[i][a];
-                const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
-                const float h = (float)eval_H(p, b, a, t, fb);
-                unsafeAtomicAdd(p.grad_balls + (int64_t)a * p.B + b, additive ? g : g * (1.f + h));
-                if (p.basis != SB_BASIS_STATIC) {
-                    const float base = p.balls[(int64_t)a * p.B + b];
-                    for (int m = 0; m < p.M; ++m) {
-                        const float dh = eval_dH(p, b, a, m, t, fb);
-                        unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b,
-                                        additive ? g * dh : g * base * dh);
-                    }
-                }
+                unsafeAtomicAdd(p.grad_balls + (int64_t)a * p.B + b, gb[a]);
+                if (MREG > 0)
+                    for (int m = 0; m < MREG; ++m)
+                        unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b, gd[a][m]);
             }
         }
     }
 }
 
-template <int NW, int G, int UCAP, int KERNEL>
+template <int UROW, int KERNEL, int MREG>
 static hipError_t launch_adj_t(const OpParams& p, hipStream_t st) {
     int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((adjoint_kernel<NW, G, UCAP, KERNEL>), dim3((unsigned)grid), dim3(64 * NW), 0,
-                       st, p);
+    hipLaunchKernelGGL((adjoint_kernel<UROW, KERNEL, MREG>), dim3((unsigned)grid), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
-    // the host's work decomposition (n_sblocks, n_groups) must match the instance
-    if (kernel == SB_KERNEL_UNIFORM) {
-        if (tc.nw == 4 && tc.g == 256 && tc.ucap == 64) return launch_adj_t<4, 256, 64, 0>(p, st);
-        if (tc.nw == 2 && tc.g == 128 && tc.ucap == 96) return launch_adj_t<2, 128, 96, 0>(p, st);
-        if (tc.nw == 4 && tc.g == 128 && tc.ucap == 64) return launch_adj_t<4, 128, 64, 0>(p, st);
-    } else {
-        if (tc.nw == 4 && tc.g == 128 && tc.ucap == 96) return launch_adj_t<4, 128, 96, 1>(p, st);
+    // register accumulators for the Fourier coefficients when they fit (K <= 2)
+    const bool reg = p.basis == SB_BASIS_FOURIER && p.M == 4;
+    if (tc.ucap == 128) {
+        if (kernel == SB_KERNEL_UNIFORM)
+            return reg ? launch_adj_t<128, 0, 4>(p, st) : launch_adj_t<128, 0, 0>(p, st);
+        return reg ? launch_adj_t<128, 1, 4>(p, st) : launch_adj_t<128, 1, 0>(p, st);
     }
+    if (tc.ucap == 192 && kernel == SB_KERNEL_GAUSS)
+        return reg ? launch_adj_t<192, 1, 4>(p, st) : launch_adj_t<192, 1, 0>(p, st);
     return hipErrorInvalidValue;
 }
 

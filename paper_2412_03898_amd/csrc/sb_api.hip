@@ -27,10 +27,13 @@ static int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-// Per-device scratch: the sticky flag word and the loss partials.
+// Per-device scratch: the sticky flag word, the loss partials, and the
+// ordering buffers (grown on demand, kept until the process ends).
 struct DeviceState {
     unsigned* flags = nullptr;
     double* partials = nullptr;
+    void* order_buf = nullptr;
+    size_t order_bytes = 0;
 };
 
 static std::mutex g_mu;
@@ -111,16 +114,27 @@ static int validate_batch(const sb_batch* batch, Shape& sh) {
     return SB_OK;
 }
 
-// Tile configuration per trace kernel (balls per group, waves per block, tile length).
-static TileCfg pick_tiles(int kernel) {
+// Tile configurations.  Forward: 4 waves x 64 sensors per block, chunks of 256
+// balls, 128-sample columns.  Adjoint: 128-sample residual rows (192 for the
+// Gaussian ball, whose windows are wider).
+static TileCfg pick_forward_tiles(int kernel) {
     TileCfg tc;
-    if (kernel == SB_KERNEL_UNIFORM) { tc.nw = 4; tc.g = 128; tc.ucap = 64; }
-    else { tc.nw = 4; tc.g = 128; tc.ucap = 96; }
+    tc.nw = 4;
+    tc.g = 256;
+    tc.ucap = 128;
+    (void)kernel;
     return tc;
 }
 
-static void fill_params(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh,
-                        const TileCfg& tc) {
+static TileCfg pick_adjoint_tiles(int kernel) {
+    TileCfg tc;
+    tc.nw = 4;
+    tc.g = 256;
+    tc.ucap = kernel == SB_KERNEL_UNIFORM ? 128 : 192;
+    return tc;
+}
+
+static void fill_common(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh) {
     memset(&p, 0, sizeof p);
     p.B = sh.B;
     p.S = (int32_t)sh.S;
@@ -132,18 +146,53 @@ static void fill_params(OpParams& p, const sb_config* cfg, const sb_batch* batch
     p.inv_delta = cfg->fs / cfg->c;
     p.t0fs = cfg->t0 * cfg->fs;
     p.delta = (float)(cfg->c / cfg->fs);
-    p.n_sblocks = (int32_t)((sh.S + 64 * tc.nw - 1) / (64 * tc.nw));
     p.n_scenes = batch->n_scenes;
-    int64_t items = 0;
     for (int i = 0; i < batch->n_scenes; ++i) {
         Scene& s = p.scenes[i];
         s.ball0 = batch->ball_offset[i];
         s.n_balls = (int32_t)(batch->ball_offset[i + 1] - batch->ball_offset[i]);
         s.frame0 = (int32_t)batch->frame_offset[i];
         s.n_frames = (int32_t)(batch->frame_offset[i + 1] - batch->frame_offset[i]);
+    }
+}
+
+// Forward items: (scene, frame, chunk of tc.g balls, block of 64*nw sensors).
+static void fill_forward(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh,
+                         const TileCfg& tc) {
+    fill_common(p, cfg, batch, sh);
+    p.n_sblocks = (int32_t)((sh.S + 64 * tc.nw - 1) / (64 * tc.nw));
+    int64_t items = 0;
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        Scene& s = p.scenes[i];
         s.n_groups = (s.n_balls + tc.g - 1) / tc.g;
         s.item0 = items;
         items += (int64_t)s.n_frames * s.n_groups * p.n_sblocks;
+    }
+    p.n_items = items;
+}
+
+// Adjoint items: (scene, chunk of 256 balls, split of the sensors); frames inside.
+// The sensors are split so that there are enough items to fill the chip.
+static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh) {
+    fill_common(p, cfg, batch, sh);
+    int64_t chunks = 0;
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        Scene& s = p.scenes[i];
+        s.n_groups = (s.n_balls + 255) / 256;
+        if (s.n_frames > 0) chunks += s.n_groups;
+    }
+    const int64_t target = 4096;
+    int64_t n_split = chunks > 0 ? (target + chunks - 1) / chunks : 1;
+    const int64_t max_split = sh.S >= 8 ? sh.S / 8 : 1;
+    if (n_split > max_split) n_split = max_split;
+    if (n_split < 1) n_split = 1;
+    p.s_per_split = (int32_t)((sh.S + n_split - 1) / n_split);
+    p.n_sblocks = (int32_t)((sh.S + p.s_per_split - 1) / p.s_per_split);
+    int64_t items = 0;
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        Scene& s = p.scenes[i];
+        s.item0 = items;
+        if (s.n_frames > 0) items += (int64_t)s.n_groups * p.n_sblocks;
     }
     p.n_items = items;
 }
@@ -203,9 +252,9 @@ int slingbag_forward(const sb_config* cfg, const sb_batch* batch, const float* b
     hipError_t e = launch_fill(signals, sh.F * sh.S * sh.T, 0.f, s);
     if (e != hipSuccess) return hip_fail(e, "fill(signals)");
     if (sh.B == 0 || sh.F == 0) return SB_OK;
-    const TileCfg tc = pick_tiles(cfg->kernel);
+    const TileCfg tc = pick_forward_tiles(cfg->kernel);
     OpParams p;
-    fill_params(p, cfg, batch, sh, tc);
+    fill_forward(p, cfg, batch, sh, tc);
     p.balls = balls;
     p.deform = deform;
     p.frame_t = frame_t;
@@ -259,9 +308,9 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* b
         e = launch_fill(grad_deform, 5 * (int64_t)sh.M * sh.B, 0.f, s);
     if (e != hipSuccess) return hip_fail(e, "fill(grads)");
     if (sh.B == 0 || sh.F == 0) return SB_OK;
-    const TileCfg tc = pick_tiles(cfg->kernel);
+    const TileCfg tc = pick_adjoint_tiles(cfg->kernel);
     OpParams p;
-    fill_params(p, cfg, batch, sh, tc);
+    fill_adjoint(p, cfg, batch, sh);
     p.balls = balls;
     p.deform = deform;
     p.frame_t = frame_t;
@@ -289,6 +338,60 @@ int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n
     hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
     time_mark(kTimeAdam, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adam kernel");
+    return SB_OK;
+}
+
+int slingbag_order(const sb_batch* batch, const float* balls, int32_t* perm, void* stream) {
+    Shape sh;
+    int st = validate_batch(batch, sh);
+    if (st) return st;
+    if (sh.B > (int64_t)INT32_MAX) return fail(SB_ERR_SHAPE, "too many balls to order (%lld)", (long long)sh.B);
+    if (sh.B > 0 && (!balls || !perm)) return fail(SB_ERR_INVALID_ARG, "balls / perm is NULL");
+    if (sh.B == 0) return SB_OK;
+    DeviceState* ds;
+    if ((st = device_state(&ds))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)sh.B;
+    size_t temp_bytes = 0;
+    hipError_t e = sort_pairs(nullptr, temp_bytes, nullptr, nullptr, nullptr, nullptr, n, s);
+    if (e != hipSuccess) return hip_fail(e, "radix sort sizing");
+    const size_t keys_bytes = ((size_t)n * 8 + 255) & ~(size_t)255;
+    const size_t idx_bytes = ((size_t)n * 4 + 255) & ~(size_t)255;
+    const size_t need = 2 * keys_bytes + idx_bytes + temp_bytes + 256;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (ds->order_bytes < need) {
+            if (ds->order_buf) {
+                e = hipStreamSynchronize(s);
+                if (e == hipSuccess) e = hipFree(ds->order_buf);
+                if (e != hipSuccess) return hip_fail(e, "release ordering scratch");
+                ds->order_buf = nullptr;
+                ds->order_bytes = 0;
+            }
+            e = hipMalloc(&ds->order_buf, need);
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(ordering scratch)");
+            ds->order_bytes = need;
+        }
+    }
+    char* base = (char*)ds->order_buf;
+    unsigned long long* kin = (unsigned long long*)base;
+    unsigned long long* kout = (unsigned long long*)(base + keys_bytes);
+    int* idx = (int*)(base + 2 * keys_bytes);
+    void* temp = base + 2 * keys_bytes + idx_bytes;
+    e = launch_morton_keys(balls, sh.B, batch->ball_offset, batch->n_scenes, kin, idx, s);
+    if (e == hipSuccess) e = sort_pairs(temp, temp_bytes, kin, kout, idx, (int*)perm, n, s);
+    if (e != hipSuccess) return hip_fail(e, "ordering kernels");
+    return SB_OK;
+}
+
+int slingbag_permute(const float* src, float* dst, int64_t rows, int64_t n, const int32_t* perm,
+                     void* stream) {
+    if (rows < 0 || n < 0) return fail(SB_ERR_SHAPE, "rows and n must be >= 0");
+    if (rows * n == 0) return SB_OK;
+    if (!src || !dst || !perm) return fail(SB_ERR_INVALID_ARG, "src / dst / perm is NULL");
+    if (src == dst) return fail(SB_ERR_INVALID_ARG, "dst must not alias src");
+    hipError_t e = launch_gather_rows(src, dst, rows, n, perm, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "permute kernel");
     return SB_OK;
 }
 

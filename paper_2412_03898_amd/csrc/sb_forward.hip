@@ -1,15 +1,22 @@
 // Forward operator: per (ball, sensor, frame) scatter of a short sampled trace.
 //
-// Work item = (scene, frame, group of G consecutive balls, block of 64*NW sensors).
-// A block stages its group's deformed balls (Eq. 1, recomputed here) in LDS and
-// finds the group's bounding-box centre.  Each wave owns 64 sensors, one per lane,
-// and each lane owns one column of the wave's LDS trace tile: samples
-// [o, o + UCAP) of its sensor, with o centred on the arrival time from the group
-// centre.  Balls are wave-uniform; each lane adds the ball's window into its own
-// column (no LDS atomics, no bank conflicts: column c lives in bank c mod 32).
-// After the group, each lane adds the touched part of its column to the global
-// trace with FP32 atomics.  A window that does not fit the tile (a spread-out
-// group) is added to global memory directly.
+// Work item = (scene, frame, chunk of G consecutive balls, block of 64*NW
+// sensors).  The block stages the chunk's deformed balls (Eq. 1, recomputed
+// here) in LDS and splits the chunk into sub-groups: runs of consecutive balls
+// that share a cell of the canonical grid at a level chosen so that a
+// sub-group's arrival-time spread fits the LDS tile.  With balls in Morton order
+// every such cell is one run.
+//
+// Each wave owns 64 sensors, one per lane, and each lane owns one column of the
+// wave's LDS trace tile T[UCAP][64] (column c lives in bank c mod 32: no
+// conflicts while lanes add their windows at different samples).  Per
+// sub-group, each lane places its column at the arrival sample of the
+// sub-group's bounding box, adds the windows of the sub-group's balls, and the
+// wave then flushes the tile: each 64-sample block is transposed in place (swap
+// pairs along diagonals, conflict-free) so that one row holds 64 consecutive
+// samples of one sensor, and is added to the global trace with one coalesced
+// FP32 atomic per row.  A window that does not fit the tile is added to global
+// memory directly.
 //
 // Trace of one ball in sample units (tau = (r - c t0)/delta, rho = R_f/delta):
 // with boundaries x_m = tau - k_lo + 1/2 - m, m = 0..W, between samples,
@@ -30,109 +37,261 @@ __device__ inline float trace_coef(const BallF& bl, double r, float delta) {
     return (float)((double)bl.amp * bl.rho * bl.rho * (double)delta / (2.0 * r));
 }
 
+// Add one ball's window (W samples from boundary x0 on) to a tile column
+// (stride 64 floats) or, when out of the tile, straight to the global row.
+template <int KERNEL>
+__device__ inline void add_window(float* c, int W, float x, float rho, float C) {
+    if (KERNEL == SB_KERNEL_UNIFORM) {
+        float Qp = rho * rho;
+        int j = 0;
+        for (; j + 4 <= W; j += 4) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x -= 1.f;
+                const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
+                const float Q = q * q;
+                v[u] = C * (Qp - Q);
+                Qp = Q;
+            }
+            float o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) o[u] = c[(j + u) * 64];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[(j + u) * 64] = o[u] + v[u];
+        }
+        for (; j < W; ++j) {
+            x -= 1.f;
+            const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
+            const float Q = q * q;
+            c[j * 64] += C * (Qp - Q);
+            Qp = Q;
+        }
+    } else {
+        const float ce = -1.f / (2.f * rho * rho);
+        float Ep = __expf(x * x * ce);
+        for (int j = 0; j < W; ++j) {
+            x -= 1.f;
+            const float E = __expf(x * x * ce);
+            c[j * 64] += C * (E - Ep);
+            Ep = E;
+        }
+    }
+}
+
+template <int KERNEL>
+__device__ inline bool add_window_global(float* row, int klo, int T, int W, float x, float rho,
+                                         float C) {
+    bool clipped = false;
+    float Qp = rho * rho;
+    const float ce = -1.f / (2.f * rho * rho);
+    float Ep = (KERNEL == SB_KERNEL_UNIFORM) ? 0.f : __expf(x * x * ce);
+    for (int j = 0; j < W; ++j) {
+        x -= 1.f;
+        float v;
+        if (KERNEL == SB_KERNEL_UNIFORM) {
+            const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
+            const float Q = q * q;
+            v = C * (Qp - Q);
+            Qp = Q;
+        } else {
+            const float E = __expf(x * x * ce);
+            v = C * (E - Ep);
+            Ep = E;
+        }
+        const int k = klo + j;
+        if (v != 0.f) {
+            if (k >= 0 && k < T) unsafeAtomicAdd(row + k, v);
+            else clipped = true;
+        }
+    }
+    return clipped;
+}
+
 template <int NW, int G, int UCAP, int KERNEL>
 __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
+    static_assert(UCAP % 64 == 0, "tile length must be a multiple of 64");
     __shared__ BallF sball[G];
+    __shared__ uint32_t scell[G][3];     // canonical grid coordinates of the base positions
+    __shared__ int sub_start[G + 1];     // sub-group boundaries within the chunk
+    __shared__ int wave_cnt[NW];
+    __shared__ float sred[NW][2];
+    __shared__ int s_nsub, s_level;
     __shared__ float tile[NW][UCAP][64];
-    __shared__ double sred[NW * 6];
-    __shared__ double scen[3];
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    float* col = &tile[wid][0][lane];
-    for (int k = 0; k < UCAP; ++k) col[k * 64] = 0.f;
+    float* const tw = &tile[wid][0][0];
+    for (int k = 0; k < UCAP; ++k) tw[k * 64 + lane] = 0.f;
 
     for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
         const Item it = decode_item(p, item);
         const Scene& sc = p.scenes[it.scene];
         const int gf = sc.frame0 + it.frame;
         const float t = p.frame_t[gf];
-        __syncthreads();   // previous item's readers of sball/scen are done
-        int nb;
-        stage_group<NW, G>(p, sc, it.group, t, sball, sred, scen, nb);
+        const int64_t first = sc.ball0 + (int64_t)it.group * G;
+        const int nb = min(G, sc.n_balls - it.group * G);
+        __syncthreads();   // the previous item is done with sball/scell/sub_start
+
+        // ---- stage the chunk: deformed balls, grid cells, size and displacement bounds
+        double fb[2 * SB_MAX_FOURIER];
+        if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
+        float rho_max = 0.f, disp_max = 0.f;
+        for (int i = tid; i < G; i += 64 * NW) {
+            BallF bl;
+            uint32_t c3[3] = {0u, 0u, 0u};
+            if (i < nb) {
+                const int64_t b = first + i;
+                if (!deform_ball(p, b, t, fb, bl)) raise_flag(p.flags, SB_FLAG_NONFINITE);
+                const double bx = p.balls[b], by = p.balls[p.B + b], bz = p.balls[2 * p.B + b];
+                c3[0] = grid_coord(bx);
+                c3[1] = grid_coord(by);
+                c3[2] = grid_coord(bz);
+                if (bl.rho >= 0.0) {
+                    rho_max = fmaxf(rho_max, bl.rhof);
+                    const double dd = fmax(fabs(bl.x - bx), fmax(fabs(bl.y - by), fabs(bl.z - bz)));
+                    disp_max = fmaxf(disp_max, (float)dd);
+                }
+            } else {
+                bl.x = bl.y = bl.z = 0.0;
+                bl.rho = -1.0;
+                bl.rhof = -1.f;
+                bl.amp = 0.f;
+            }
+            sball[i] = bl;
+            scell[i][0] = c3[0];
+            scell[i][1] = c3[1];
+            scell[i][2] = c3[2];
+        }
+        rho_max = wave_max(rho_max);
+        disp_max = wave_max(disp_max);
+        if (lane == 0) { sred[wid][0] = rho_max; sred[wid][1] = disp_max; }
+        __syncthreads();
+        if (tid == 0) {
+            float rm = 0.f, dm = 0.f;
+            for (int w = 0; w < NW; ++w) { rm = fmaxf(rm, sred[w][0]); dm = fmaxf(dm, sred[w][1]); }
+            // largest grid level whose cell keeps the arrival spread inside the tile:
+            // a sub-group's deformed bounding box has a diagonal of at most
+            // sqrt(3) (side + 2 dm) (dm: largest per-axis displacement), and a
+            // column must hold that spread plus one window (2h + 2) and the
+            // origin margins (4 samples), with 2 samples to spare.
+            const double h = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rm : (double)kGaussCut * rm;
+            const double room = ((double)(UCAP - 8) - 2.0 * h) * (double)p.delta -
+                                2.0 * 1.7320508075688772 * (double)dm;
+            int level = 0;
+            while (level < kGridBits - 1 && 1.7320508075688772 * kGridQuantum * (double)(1 << (level + 1)) <= room)
+                ++level;
+            s_level = level;
+        }
+        __syncthreads();
+        // ---- sub-groups: runs of equal cell at the chosen level (block-wide compaction)
+        {
+            const int level = s_level;
+            const int i = tid;                 // G == 64 * NW (one ball per thread)
+            bool flag = false;
+            if (i < nb) {
+                flag = (i == 0) || ((scell[i][0] >> level) != (scell[i - 1][0] >> level)) ||
+                       ((scell[i][1] >> level) != (scell[i - 1][1] >> level)) ||
+                       ((scell[i][2] >> level) != (scell[i - 1][2] >> level));
+            }
+            const unsigned long long m = __ballot(flag);
+            const int before = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) wave_cnt[wid] = __popcll(m);
+            __syncthreads();
+            int base = 0;
+            for (int w = 0; w < wid; ++w) base += wave_cnt[w];
+            if (flag) sub_start[base + before] = i;
+            if (tid == 0) {
+                int tot = 0;
+                for (int w = 0; w < NW; ++w) tot += wave_cnt[w];
+                s_nsub = tot;
+                sub_start[tot] = nb;
+            }
+            __syncthreads();
+        }
+        const int nsub = s_nsub;
 
         const int s = it.sblock * 64 * NW + wid * 64 + lane;
         const bool active = s < p.S;
         double sx = 0.0, sy = 0.0, sz = 0.0;
         if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
-        const int o = tile_origin(p, scen, sx, sy, sz, UCAP);
-        int kmin = UCAP, kmax = -1;
         float* out_row = p.signals + ((int64_t)gf * p.S + (active ? s : 0)) * p.T;
+        const int64_t frame_base = (int64_t)gf * p.S * p.T;
         bool clipped = false;
 
-        for (int bi = 0; bi < nb; ++bi) {
-            const BallF bl = sball[bi];
-            if (bl.rho < 0.0 || !active) continue;
-            const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl, bl.x - sx, bl.y - sy, bl.z - sz);
-            if (!w.ok) {
-                raise_flag(p.flags, SB_FLAG_GEOMETRY);
-                continue;
+        for (int sg = 0; sg < nsub; ++sg) {
+            const int i0 = sub_start[sg], i1 = sub_start[sg + 1];
+            // bounding box (rounded outwards) and largest size of the sub-group
+            float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+            float rmax = 0.f;
+            for (int i = i0 + lane; i < i1; i += 64) {
+                const BallF& bl = sball[i];
+                if (bl.rho < 0.0) continue;
+                lo[0] = fminf(lo[0], __double2float_rd(bl.x)); hi[0] = fmaxf(hi[0], __double2float_ru(bl.x));
+                lo[1] = fminf(lo[1], __double2float_rd(bl.y)); hi[1] = fmaxf(hi[1], __double2float_ru(bl.y));
+                lo[2] = fminf(lo[2], __double2float_rd(bl.z)); hi[2] = fmaxf(hi[2], __double2float_ru(bl.z));
+                rmax = fmaxf(rmax, bl.rhof);
             }
-            if (!w.in_range) {          // arrival far outside any record: nothing to add
-                clipped = true;
-                continue;
-            }
-            const float rho = bl.rhof;
-            const float C = trace_coef<KERNEL>(bl, w.r, p.delta);
-            const int W = w.W;
-            const int tl = w.klo - o;
-            float x = (float)w.a0;
-            if (tl >= 0 && tl + W <= UCAP) {
-                float* c = col + tl * 64;
-                kmin = min(kmin, tl);
-                kmax = max(kmax, tl + W - 1);
-                if (KERNEL == SB_KERNEL_UNIFORM) {
-                    float Qp = rho * rho;
-                    for (int j = 0; j < W; ++j) {
-                        x -= 1.f;
-                        const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
-                        const float Q = q * q;
-                        c[j * 64] += C * (Qp - Q);
-                        Qp = Q;
-                    }
+            for (int a = 0; a < 3; ++a) { lo[a] = wave_min(lo[a]); hi[a] = wave_max(hi[a]); }
+            rmax = wave_max(rmax);
+            if (!(lo[0] <= hi[0])) continue;          // no valid ball in this sub-group
+            const double hmax = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rmax : (double)kGaussCut * rmax;
+            double dmin, dmax;
+            box_distance_range(lo, hi, sx, sy, sz, dmin, dmax);
+            // column origin: every window of the sub-group starts at or after o + 1
+            const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
+            const int o = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
+            int kmax = -1;
+
+            for (int i = i0; i < i1; ++i) {
+                const BallF bl = sball[i];
+                if (bl.rho < 0.0 || !active) continue;
+                const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, bl.x - sx, bl.y - sy, bl.z - sz);
+                if (!w.ok) {
+                    raise_flag(p.flags, SB_FLAG_GEOMETRY);
+                    continue;
+                }
+                if (!w.in_range) {          // arrival far outside any record: nothing to add
+                    clipped = true;
+                    continue;
+                }
+                const float C = trace_coef<KERNEL>(bl, w.r, p.delta);
+                const int tl = w.klo - o;
+                const float x0 = (float)w.a0;
+                if (tl >= 0 && tl + w.W <= UCAP) {
+                    add_window<KERNEL>(tw + tl * 64 + lane, w.W, x0, bl.rhof, C);
+                    kmax = max(kmax, tl + w.W - 1);
                 } else {
-                    const float ce = -1.f / (2.f * rho * rho);
-                    float Ep = expf(x * x * ce);
-                    for (int j = 0; j < W; ++j) {
-                        x -= 1.f;
-                        const float E = expf(x * x * ce);
-                        c[j * 64] += C * (E - Ep);
-                        Ep = E;
+                    clipped |= add_window_global<KERNEL>(out_row, w.klo, p.T, w.W, x0, bl.rhof, C);
+                }
+            }
+
+            // ---- flush: transpose each touched 64-sample block in place, then one
+            // coalesced atomic per (sensor, block)
+            const int nblk = (wave_max_i(kmax) + 64) >> 6;
+            for (int q = 0; q < nblk; ++q) {
+                float* blk = tw + q * 64 * 64;
+                wave_lds_sync();
+                for (int d = 1; d <= 32; ++d) {
+                    if (d < 32 || lane < 32) {
+                        const int c = (lane + d) & 63;
+                        const float a = blk[lane * 64 + c];
+                        const float b = blk[c * 64 + lane];
+                        blk[lane * 64 + c] = b;
+                        blk[c * 64 + lane] = a;
                     }
                 }
-            } else {
-                // window outside the tile: add straight to the global trace
-                float Qp = rho * rho;
-                const float ce = -1.f / (2.f * rho * rho);
-                float Ep = (KERNEL == SB_KERNEL_UNIFORM) ? 0.f : expf(x * x * ce);
-                for (int j = 0; j < W; ++j) {
-                    x -= 1.f;
-                    float v;
-                    if (KERNEL == SB_KERNEL_UNIFORM) {
-                        const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
-                        const float Q = q * q;
-                        v = C * (Qp - Q);
-                        Qp = Q;
-                    } else {
-                        const float E = expf(x * x * ce);
-                        v = C * (E - Ep);
-                        Ep = E;
-                    }
-                    const int k = w.klo + j;
-                    if (v != 0.f) {
-                        if (k >= 0 && k < p.T) unsafeAtomicAdd(out_row + k, v);
+                wave_lds_sync();
+                for (int a = 0; a < 64; ++a) {
+                    const float v = blk[a * 64 + lane];
+                    blk[a * 64 + lane] = 0.f;
+                    const int sa = __builtin_amdgcn_readlane(s, a);
+                    const int oa = __builtin_amdgcn_readlane(o, a);
+                    const int k = oa + q * 64 + lane;
+                    if (v != 0.f && sa < p.S) {
+                        if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + frame_base + (int64_t)sa * p.T + k, v);
                         else clipped = true;
                     }
                 }
-            }
-        }
-        // flush the touched part of this lane's column, leaving it zero
-        for (int k = kmin; k <= kmax; ++k) {
-            const float v = col[k * 64];
-            col[k * 64] = 0.f;
-            const int kg = o + k;
-            if (v != 0.f) {
-                if (kg >= 0 && kg < p.T) unsafeAtomicAdd(out_row + kg, v);
-                else clipped = true;
             }
         }
         if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
@@ -141,6 +300,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
 
 template <int NW, int G, int UCAP, int KERNEL>
 static hipError_t launch_fwd_t(const OpParams& p, hipStream_t st) {
+    static_assert(G == 64 * NW, "one ball per thread in the sub-group compaction");
     int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((forward_kernel<NW, G, UCAP, KERNEL>), dim3((unsigned)grid), dim3(64 * NW), 0,
@@ -151,11 +311,11 @@ static hipError_t launch_fwd_t(const OpParams& p, hipStream_t st) {
 hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
     // the host's work decomposition (n_sblocks, n_groups) must match the instance
     if (kernel == SB_KERNEL_UNIFORM) {
+        if (tc.nw == 4 && tc.g == 256 && tc.ucap == 128) return launch_fwd_t<4, 256, 128, 0>(p, st);
         if (tc.nw == 4 && tc.g == 256 && tc.ucap == 64) return launch_fwd_t<4, 256, 64, 0>(p, st);
-        if (tc.nw == 2 && tc.g == 128 && tc.ucap == 96) return launch_fwd_t<2, 128, 96, 0>(p, st);
-        if (tc.nw == 4 && tc.g == 128 && tc.ucap == 64) return launch_fwd_t<4, 128, 64, 0>(p, st);
+        if (tc.nw == 2 && tc.g == 128 && tc.ucap == 128) return launch_fwd_t<2, 128, 128, 0>(p, st);
     } else {
-        if (tc.nw == 4 && tc.g == 128 && tc.ucap == 96) return launch_fwd_t<4, 128, 96, 1>(p, st);
+        if (tc.nw == 4 && tc.g == 256 && tc.ucap == 128) return launch_fwd_t<4, 256, 128, 1>(p, st);
     }
     return hipErrorInvalidValue;
 }

@@ -37,7 +37,8 @@ struct OpParams {
     float delta;             // c / fs   (metres per sample)
     int32_t S, T;
     int32_t basis, pos_mode, n_terms, M;
-    int32_t n_sblocks;       // sensor blocks per (frame, group)
+    int32_t n_sblocks;       // forward: sensor blocks per (frame, chunk); adjoint: sensor splits
+    int32_t s_per_split;     // adjoint: sensors per split
     int32_t n_scenes;
     Scene scenes[SB_MAX_SCENES];
 };
@@ -72,6 +73,24 @@ __device__ inline Item decode_item(const OpParams& p, int64_t item) {
     int64_t q = local / p.n_sblocks;
     it.group = (int)(q % sc.n_groups);
     it.frame = (int)(q / sc.n_groups);
+    return it;
+}
+
+// Adjoint work item -> (scene, chunk of 64 balls, sensor split); items of one
+// scene are ordered split-major so that consecutive items share residual rows.
+struct ItemA {
+    int scene, chunk, split;
+};
+
+__device__ inline ItemA decode_item_adj(const OpParams& p, int64_t item) {
+    int i = 0;
+    while (i + 1 < p.n_scenes && p.scenes[i + 1].item0 <= item) ++i;
+    const Scene& sc = p.scenes[i];
+    const int64_t local = item - sc.item0;
+    ItemA it;
+    it.scene = i;
+    it.chunk = (int)(local % sc.n_groups);
+    it.split = (int)(local / sc.n_groups);
     return it;
 }
 
@@ -150,102 +169,116 @@ __device__ inline void raise_flag(unsigned* flags, unsigned bit) {
 }
 
 
-// Stage the deformed balls of one group (Eq. 1, recomputed per frame) into LDS
-// and find the centre of their bounding box.  Ends with a block barrier.
-template <int NW, int G>
-__device__ inline void stage_group(const OpParams& p, const Scene& sc, int group, float t,
-                                   BallF* sball, double* sred, double* scen, int& nb) {
-    const int tid = threadIdx.x;
-    const int64_t first = sc.ball0 + (int64_t)group * G;
-    nb = min(G, sc.n_balls - group * G);
-    double fb[2 * SB_MAX_FOURIER];
-    if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int i = tid; i < G; i += 64 * NW) {
-        BallF bl;
-        if (i < nb) {
-            if (!deform_ball(p, first + i, t, fb, bl)) raise_flag(p.flags, SB_FLAG_NONFINITE);
-        } else {
-            bl.x = bl.y = bl.z = 0.0;
-            bl.rho = -1.0;
-            bl.rhof = -1.f;
-            bl.amp = 0.f;
-        }
-        sball[i] = bl;
-        if (bl.rho >= 0.0) {
-            lo[0] = fmin(lo[0], bl.x); hi[0] = fmax(hi[0], bl.x);
-            lo[1] = fmin(lo[1], bl.y); hi[1] = fmax(hi[1], bl.y);
-            lo[2] = fmin(lo[2], bl.z); hi[2] = fmax(hi[2], bl.z);
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], __shfl_xor(lo[a], off));
-            hi[a] = fmax(hi[a], __shfl_xor(hi[a], off));
-        }
-    }
-    const int wid = tid >> 6, lane = tid & 63;
-    if (lane == 0)
-        for (int a = 0; a < 3; ++a) { sred[wid * 6 + a] = lo[a]; sred[wid * 6 + 3 + a] = hi[a]; }
-    __syncthreads();
-    if (tid == 0) {
-        for (int a = 0; a < 3; ++a) {
-            double l = sred[a], h = sred[3 + a];
-            for (int w = 1; w < NW; ++w) { l = fmin(l, sred[w * 6 + a]); h = fmax(h, sred[w * 6 + 3 + a]); }
-            scen[a] = (l <= h) ? 0.5 * (l + h) : 0.0;
-        }
-    }
-    __syncthreads();
+// Canonical grid for ball ordering and grouping: positions in [-1 m, 1 m) are
+// quantised to 2^-18 m (3.8 um), 19 bits per axis.  Balls sorted by the Morton
+// key of this grid (slingbag_order) make every grid cell at every level k (side
+// 2^(k-18) m) a contiguous run of balls.
+constexpr double kGridOrigin = -1.0;
+constexpr double kGridQuantum = 1.0 / 262144.0;   // 2^-18 m
+constexpr int kGridBits = 19;
+
+__host__ __device__ inline uint32_t grid_coord(double x) {
+    double q = floor((x - kGridOrigin) / kGridQuantum);
+    q = q < 0.0 ? 0.0 : (q > (double)((1u << kGridBits) - 1) ? (double)((1u << kGridBits) - 1) : q);
+    return (uint32_t)q;
 }
 
-// Tile origin of a lane: arrival sample of the group centre minus half the tile,
-// clamped so that k_lo - o and k_lo + W stay far inside int32 for in-range pairs.
-__device__ inline int tile_origin(const OpParams& p, const double* scen, double sx, double sy,
-                                  double sz, int ucap) {
-    const double cx = scen[0] - sx, cy = scen[1] - sy, cz = scen[2] - sz;
-    const double tau_c = sqrt(cx * cx + cy * cy + cz * cz) * p.inv_delta - p.t0fs;
-    return (int)fmin(fmax(floor(tau_c) - (double)(ucap / 2), -5.0e8), 5.0e8);
+// Ball-sensor distance: FP32 square root refined by one Newton step in FP64
+// (relative error ~1e-15, well below the FP64 decisions' needs).
+__device__ inline double dist64(double dx, double dy, double dz) {
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const float rf = __builtin_amdgcn_sqrtf((float)r2);
+    const double r0 = (double)rf;
+    const float e = (float)fma(-r0, r0, r2);
+    return r0 + (double)(e * (0.5f * __builtin_amdgcn_rcpf(rf)));
 }
 
 // Window of one (ball, sensor) pair.  tau = (r - c t0)/delta is the arrival
 // sample; the window starts at sample k_lo = floor(tau - h + 1/2) (h = rho for the
 // uniform sphere, kGaussCut*rho for the Gaussian ball) so that boundary 0,
 // x_0 = tau - k_lo + 1/2, lies in [h, h + 1), and spans W = floor(2h) + 2 samples,
-// so that boundary W lies below -h: every nonzero sample is inside.  All in FP64.
+// so that boundary W lies below -h: every nonzero sample is inside.  For the
+// uniform sphere the boundaries strictly inside (-rho, rho) are m = 1..m_hi,
+// m_hi = ceil(x_0 + rho) - 1; that decision is taken in FP64.
 template <int KERNEL>
 struct PairWin {
     double r;        // ball-sensor distance
     double a0;       // x_0
-    int klo, W;
-    bool ok;         // sensor outside the uniform ball (or r > 0 for the Gaussian ball)
+    int klo, W, m_hi;
+    bool ok;         // sensor outside the uniform ball (r > 0 for the Gaussian ball)
     bool in_range;   // |k_lo| and W small enough for int32 sample arithmetic
 };
 
 template <int KERNEL>
-__device__ inline PairWin<KERNEL> pair_window(const OpParams& p, const BallF& bl, double dx,
-                                              double dy, double dz) {
+__device__ inline PairWin<KERNEL> pair_window(const OpParams& p, double rho, double dx, double dy,
+                                              double dz) {
     PairWin<KERNEL> w;
-    w.r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
-    w.ok = (KERNEL == SB_KERNEL_UNIFORM) ? (w.r > bl.rho * (double)p.delta) : (w.r > 0.0);
-    const double tau = w.r * p.inv_delta - p.t0fs;
+    w.r = dist64(dx, dy, dz);
+    const double h = (KERNEL == SB_KERNEL_UNIFORM) ? rho : (double)kGaussCut * rho;
+    w.ok = (KERNEL == SB_KERNEL_UNIFORM) ? (w.r > rho * (double)p.delta) : (w.r > 0.0);
+    const double tau = fma(w.r, p.inv_delta, -p.t0fs);
     const double kl = floor(tau - h + 0.5);
     w.in_range = fabs(kl) < 5.0e8 && h < 1.0e6;
     w.klo = w.in_range ? (int)kl : 0;
     w.W = w.in_range ? (int)(2.0 * h) + 2 : 0;
     w.a0 = tau - kl + 0.5;
+    w.m_hi = (KERNEL == SB_KERNEL_UNIFORM && w.in_range) ? (int)ceil(w.a0 + rho) - 1 : 0;
     return w;
+}
+
+// Wave-wide reductions (all 64 lanes participate).
+__device__ inline float wave_min(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ inline float wave_max(float v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ inline int wave_max_i(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Compiler-level ordering point for LDS traffic between lanes of one wave (the
+// hardware executes a wave's LDS instructions in order).
+__device__ inline void wave_lds_sync() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Distance range [dmin, dmax] from point s to the axis-aligned box [lo, hi].
+__device__ inline void box_distance_range(const float* lo, const float* hi, double sx, double sy,
+                                          double sz, double& dmin, double& dmax) {
+    const double s[3] = {sx, sy, sz};
+    double n2 = 0.0, f2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double l = lo[a], h = hi[a];
+        const double dn = s[a] < l ? l - s[a] : (s[a] > h ? s[a] - h : 0.0);
+        const double df = fmax(fabs(s[a] - l), fabs(s[a] - h));
+        n2 += dn * dn;
+        f2 += df * df;
+    }
+    dmin = sqrt(n2);
+    dmax = sqrt(f2);
 }
 
 // ---- host-side launchers (defined in the .hip files) ----
 struct TileCfg {
-    int nw;      // waves per block (64 sensors each)
-    int g;       // balls per group
-    int ucap;    // tile length in samples
+    int nw;      // forward: waves per block (64 sensors each)
+    int g;       // forward: balls per chunk
+    int ucap;    // forward: tile length in samples; adjoint: residual row length
 };
 
 hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st);
 hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st);
+hipError_t launch_morton_keys(const float* balls, int64_t B, const int64_t* ball_offset_host,
+                              int n_scenes, unsigned long long* keys, int* idx, hipStream_t st);
+hipError_t sort_pairs(void* temp, size_t& temp_bytes, const unsigned long long* kin,
+                      unsigned long long* kout, const int* vin, int* vout, int n, hipStream_t st);
+hipError_t launch_gather_rows(const float* src, float* dst, int64_t rows, int64_t B, const int* perm,
+                              hipStream_t st);
 hipError_t launch_fill(float* ptr, int64_t n, float v, hipStream_t st);
 hipError_t launch_loss(const float* y, const float* d, float* r, int64_t n, double* partials,
                        int n_blocks, double* loss, hipStream_t st);

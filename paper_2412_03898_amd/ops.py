@@ -13,7 +13,8 @@ import torch
 from . import binding
 from .binding import Problem
 
-__all__ = ["Problem", "forward", "loss", "adjoint", "adam_", "check", "to_device"]
+__all__ = ["Problem", "forward", "loss", "adjoint", "adam_", "order", "permute", "apply_order",
+           "check", "to_device"]
 
 
 def _stream() -> int:
@@ -87,6 +88,35 @@ def adam_(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
     binding.adam(_ptr(param, "param"), _ptr(grad, "grad"), _ptr(m, "m"), _ptr(v, "v"), n,
                  float(lr), float(beta1), float(beta2), float(eps), int(step), _stream())
     return param
+
+
+def order(pb: Problem, balls):
+    """Morton permutation of every scene's balls (slingbag_order): int32 [B] on the GPU."""
+    B = pb.n_balls
+    perm = torch.empty((B,), dtype=torch.int32, device=balls.device)
+    binding.order(pb, _ptr(balls, "balls", (5, B)), _ptr(perm, "perm", (B,), torch.int32), _stream())
+    return perm
+
+
+def permute(src, perm, out=None):
+    """out[..., i] = src[..., perm[i]] over the last axis (slingbag_permute)."""
+    n = src.shape[-1]
+    rows = src.numel() // max(n, 1)
+    if out is None:
+        out = torch.empty_like(src)
+    binding.permute(_ptr(src, "src"), _ptr(out, "out"), rows, n,
+                    _ptr(perm, "perm", (n,), torch.int32), _stream())
+    return out
+
+
+def apply_order(pb: Problem, balls, deform=None):
+    """Sort balls (and their deformation coefficients) along the Morton curve on the GPU.
+    Returns (balls, deform, perm); results of every operator are unchanged up to
+    this permutation of the per-ball arrays."""
+    perm = order(pb, balls)
+    nb = permute(balls, perm)
+    nd = permute(deform, perm) if deform is not None else None
+    return nb, nd, perm
 
 
 def check() -> int:

@@ -363,18 +363,19 @@ def synthetic_residual(n_frames: int, n_sensors: int, n_samples: int, seed: int)
     return rng.normal(0.0, 1e-3, size=(n_frames, n_sensors, n_samples)).astype(np.float32)
 
 
-def morton_order(balls: np.ndarray, bits: int = 10) -> np.ndarray:
+def morton_order(balls: np.ndarray, bits: int = 19, quantum: float = 2.0 ** -18,
+                 origin: float = -1.0) -> np.ndarray:
     """Permutation that sorts balls by the Morton (Z-order) code of their centres.
 
     The operator's result does not depend on ball order; a spatially coherent
     order only makes consecutive balls arrive at nearly the same sample at
-    every sensor.  Centres are quantised to 2**bits cells per axis over their
-    bounding box.
+    every sensor.  Centres are quantised on a fixed grid (cells of `quantum`
+    metres from `origin`, `bits` bits per axis, clamped to the grid), the
+    same grid for every scene, and the sort is stable.
     """
     pos = np.asarray(balls[0:3], dtype=np.float64)
-    lo = pos.min(axis=1, keepdims=True)
-    span = np.maximum(pos.max(axis=1, keepdims=True) - lo, 1e-30)
-    q = np.minimum(((pos - lo) / span * (1 << bits)).astype(np.int64), (1 << bits) - 1)
+    q = np.floor((pos - origin) / quantum)
+    q = np.clip(q, 0, (1 << bits) - 1).astype(np.int64)
     code = np.zeros(pos.shape[1], dtype=np.int64)
     for bit in range(bits):
         for a in range(3):

@@ -265,3 +265,39 @@ def test_vessel_4d_full_size_sampled():
     rng = np.random.default_rng(7)
     res = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
     assert_grads(sub, gpu_adjoint(sub, res), oracle.adjoint(sub, res.astype(np.float64)))
+
+
+# ---------------------------------------------------------------- ordering (performance only)
+def test_order_matches_morton_definition():
+    """The GPU order is the stable sort by the Morton code of the fixed grid, per scene
+    (integer result: bit-exact against the definition written in numpy)."""
+    import torch
+    from paper_2412_03898_amd import ops
+    a = synth.workload_vessel_static(n_balls=30_000, n_sensors=4, n_samples=4096, seed=12)
+    b = synth.workload_plain(n_balls=7_000, n_sensors=4, seed=13)
+    balls = np.concatenate([a.balls, b.balls], axis=1)
+    wl = with_(a, balls=balls, ball_offset=np.array([0, 30_000, 37_000]),
+               frame_offset=np.array([0, 1, 2]), frame_t=np.zeros(2, np.float32))
+    pb = ops.Problem.from_workload(wl)
+    bt = torch.from_numpy(balls).cuda()
+    perm = ops.order(pb, bt).cpu().numpy()
+    ref = np.concatenate([synth.morton_order(a.balls), synth.morton_order(b.balls) + 30_000])
+    np.testing.assert_array_equal(perm, ref)
+    nb = ops.permute(bt, torch.from_numpy(perm).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(nb, balls[:, perm])
+
+
+def test_result_independent_of_order():
+    """Forward and gradients of a 4D scene are the same (up to the permutation) in any ball order."""
+    wl = synth.workload_vessel_4d(n_balls=3000, n_sensors=70, n_frames=3)
+    y0, _ = gpu_forward(wl)
+    ws = synth.apply_order(wl)
+    y1, _ = gpu_forward(ws)
+    assert rel_l2(y1, y0) <= 1e-6
+    rng = np.random.default_rng(8)
+    res = rng.normal(size=y0.shape).astype(np.float32)
+    g0 = gpu_adjoint(wl, res)
+    g1 = gpu_adjoint(ws, res)
+    perm = synth.morton_order(wl.balls)
+    assert rel_l2(g1[0], g0[0][:, perm]) <= 1e-5
+    assert rel_l2(g1[1], g0[1][:, :, perm]) <= 1e-5

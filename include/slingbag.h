@@ -180,6 +180,32 @@ int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n
  * SB_ERR_DEVICE_FLAG if SB_FLAG_GEOMETRY or SB_FLAG_NONFINITE was raised. */
 int slingbag_check(void* stream, uint32_t* flags);
 
+/* Tuning knobs, read by every later call on any device (process-wide).  They
+ * change speed only; results differ at most by the order of FP32 atomic
+ * additions.  The autotuner (python: paper_2412_03898_amd.tune) times the
+ * candidates on the caller's own shapes and sets the fastest.
+ *   SB_TUNE_FWD_COLUMN     forward LDS column length: 64 or 128 samples (uniform sphere)
+ *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4
+ *   SB_TUNE_ADJ_ITEMS      adjoint work items the sensor split aims for: 1 .. 2^22
+ * Unknown keys or values return SB_ERR_INVALID_ARG and change nothing. */
+#define SB_TUNE_FWD_COLUMN     1
+#define SB_TUNE_ADJ_OCCUPANCY  2
+#define SB_TUNE_ADJ_ITEMS      3
+int slingbag_tune(int key, int value);
+int slingbag_tune_get(int key, int* value);
+
+/* Autotuner: runs the forward with every forward column length and the
+ * adjoint with every (occupancy, item count) candidate on the caller's own
+ * problem (the arguments of slingbag_forward / slingbag_adjoint; signals,
+ * grad_balls and grad_deform are overwritten, the forward output serves as
+ * the adjoint's residual), times each with HIP events on `stream` (one
+ * warm-up and two timed runs), keeps the fastest setting of every knob and
+ * writes it to choice[3] (HOST: forward column, adjoint occupancy, adjoint
+ * items).  Synchronises the stream.  Not for use under graph capture. */
+int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* balls,
+                      const float* deform, const float* frame_t, const float* sensors, float* signals,
+                      float* grad_balls, float* grad_deform, int32_t* choice, void* stream);
+
 /* Opt-in timing of the main kernels with HIP events recorded on each call's
  * own stream around the kernel launch (not around the output clearing).
  * slingbag_timing(1) creates the events on the current device and starts

@@ -63,6 +63,10 @@ _SIGS = {
                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP],
     "slingbag_order": [ctypes.POINTER(Batch), _VP, _VP, _VP],
     "slingbag_permute": [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP],
+    "slingbag_tune": [ctypes.c_int, ctypes.c_int],
+    "slingbag_autotune": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP, _VP,
+                          _VP, ctypes.POINTER(ctypes.c_int32), _VP],
+    "slingbag_tune_get": [ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "slingbag_timing": [ctypes.c_int],
     "slingbag_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     "slingbag_last_error": [],
@@ -182,6 +186,27 @@ def check(stream: int = 0) -> int:
     if st != SB_OK:
         raise SlingbagError(st, last_error())
     return int(flags.value)
+
+
+SB_TUNE_FWD_COLUMN, SB_TUNE_ADJ_OCCUPANCY, SB_TUNE_ADJ_ITEMS = 1, 2, 3
+
+
+def tune(key: int, value: int):
+    _check(load().slingbag_tune(int(key), int(value)))
+
+
+def autotune(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, signals: int,
+             grad_balls: int, grad_deform: int, stream: int = 0) -> tuple:
+    c = (ctypes.c_int32 * 3)()
+    _check(load().slingbag_autotune(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), balls, deform, frame_t,
+                                    sensors, signals, grad_balls, grad_deform, c, stream))
+    return int(c[0]), int(c[1]), int(c[2])
+
+
+def tune_get(key: int) -> int:
+    v = ctypes.c_int(0)
+    _check(load().slingbag_tune_get(int(key), ctypes.byref(v)))
+    return int(v.value)
 
 
 def timing(enable: bool):

@@ -31,55 +31,19 @@
 namespace sb {
 
 constexpr int kAdjChunk = 256;   // balls per block item (4 waves x 64 lanes)
+constexpr int kAdjMaxSplit = 256;   // sensors per item at most
 
-// Per-lane gather of one pair's window from a row reader rd(m) = residual at
-// sample k_lo + m.  Returns the three sums of the uniform sphere (Sw, St, Sr) or
-// of the Gaussian ball (S0, S1, S2).
-template <int KERNEL, typename Reader>
-__device__ inline void gather_window(const PairWin<KERNEL>& w, float rho, Reader rd, float& A,
-                                     float& Bs, float& Cs) {
-    float x = (float)w.a0;
-    if (KERNEL == SB_KERNEL_UNIFORM) {
-        const float r0 = rd(0);
-        float rp = r0, sw = 0.f, st = 0.f;
-        for (int m = 1; m <= w.m_hi; ++m) {
-            x -= 1.f;
-            const float rm = rd(m);
-            const float dr = rm - rp;
-            rp = rm;
-            sw = fmaf(x * x, dr, sw);
-            st = fmaf(x, dr, st);
-        }
-        const float sr = rp - r0;
-        A = fmaf(-rho * rho, sr, sw);
-        Bs = st;
-        Cs = sr;
-    } else {
-        const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale
-        float rp = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
-        for (int m = 0; m <= w.W; ++m) {
-            const float rm = (m < w.W) ? rd(m) : 0.f;
-            const float dr = rm - rp;
-            rp = rm;
-            const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
-            s0 += e;
-            s1 = fmaf(x, e, s1);
-            s2 = fmaf(x * x, e, s2);
-            x -= 1.f;
-        }
-        A = s0;
-        Bs = s1;
-        Cs = s2;
-    }
-}
-
-template <int UROW, int KERNEL, int MREG>
-__global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
+template <int UROW, int KERNEL, int MREG, int OCC>
+__global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
     static_assert(UROW % 64 == 0, "row length must be a multiple of 64");
     constexpr int NQ = UROW / 64;
     __shared__ float rowbuf[4][UROW];
     __shared__ float sR[kAdjChunk];
     __shared__ int sperm[kAdjChunk];
+    // per wave, per sensor of the split: row origin and coordinates
+    __shared__ int s_org[4][kAdjMaxSplit];
+    __shared__ float s_sx[4][kAdjMaxSplit], s_sy[4][kAdjMaxSplit], s_sz[4][kAdjMaxSplit];
+    __shared__ double s_fb[4][2 * SB_MAX_FOURIER];     // Fourier basis of the wave's frame
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     float* const row = rowbuf[wid];
@@ -92,7 +56,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
         const int nb = min(kAdjChunk, sc.n_balls - it.chunk * kAdjChunk);
         const int64_t first = sc.ball0 + (int64_t)it.chunk * kAdjChunk;
         const int s_begin = it.split * p.s_per_split;
-        const int s_end = min(p.S, s_begin + p.s_per_split);
+        const int ns = min(p.S - s_begin, p.s_per_split);     // sensors of this split (<= kAdjMaxSplit)
 
         // ---- rank the chunk's balls by base size; wave w takes ranks 64w..64w+63
         __syncthreads();
@@ -100,6 +64,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
         sR[tid] = Ri;
         __syncthreads();
         int rank = 0;
+#pragma unroll 8
         for (int j = 0; j < kAdjChunk; ++j) {
             const float Rj = sR[j];
             rank += (Rj < Ri) || (Rj == Ri && j < tid);
@@ -109,6 +74,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
         const int li = sperm[wid * 64 + lane];
         const bool valid = li < nb;
         const int64_t b = first + (valid ? li : 0);
+        // sensor coordinates of the split (float, as given)
+        for (int j = lane; j < ns; j += 64) {
+            s_sx[wid][j] = p.sensors[s_begin + j];
+            s_sy[wid][j] = p.sensors[p.S + s_begin + j];
+            s_sz[wid][j] = p.sensors[2 * p.S + s_begin + j];
+        }
 
         float gb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         float gd[5][MREG > 0 ? MREG : 1];
@@ -118,11 +89,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
         for (int f = 0; f < sc.n_frames; ++f) {
             const int gf = sc.frame0 + f;
             const float t = p.frame_t[gf];
+            const double* fb = s_fb[wid];
+            wave_lds_sync();
+            if (p.basis == SB_BASIS_FOURIER) fourier_basis_lanes(t, p.n_terms, s_fb[wid], lane);
+            wave_lds_sync();
             BallF bl;
             bool live = false;
             if (valid) {
-                double fb[2 * SB_MAX_FOURIER];
-                if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
                 live = deform_ball(p, b, t, fb, bl);
                 if (!live) raise_flag(p.flags, SB_FLAG_NONFINITE);
             }
@@ -139,99 +112,158 @@ __global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
             rmax = wave_max(rmax);
             if (!(lo[0] <= hi[0])) continue;           // no live ball in this wave
             const double hmax = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rmax : (double)kGaussCut * rmax;
+            // row origins of all sensors of the split, one sensor per lane: every
+            // window of the wave starts at or after o + 1
+            wave_lds_sync();
+            for (int j = lane; j < ns; j += 64) {
+                double dmin, dmax;
+                box_distance_range(lo, hi, (double)s_sx[wid][j], (double)s_sy[wid][j], (double)s_sz[wid][j],
+                                   dmin, dmax);
+                const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
+                s_org[wid][j] = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
+            }
+            wave_lds_sync();
 
+            // per-ball constants of this frame
+            const float rho = live ? bl.rhof : 0.f;
+            const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
+            const double h_half = h - 0.5;
+            const double r_in = bl.rho * (double)delta;       // sensor must be farther than this
+            const int W = live ? (int)(2.0 * h) + 2 : 0;
+            const bool w_ok = live && h < 1.0e6;
+            // wave-uniform trip count of the gather loop
+            const int n_it = wave_max_i(KERNEL == SB_KERNEL_UNIFORM ? W - 1 : W + 1);
             const float* res_frame = p.residual + (int64_t)gf * p.S * p.T;
             float g5[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 
-            // row origin of a sensor: every window of the wave starts at or after o + 1
-            auto origin = [&](int s) -> int {
-                double dmin, dmax;
-                box_distance_range(lo, hi, (double)p.sensors[s], (double)p.sensors[p.S + s],
-                                   (double)p.sensors[2 * p.S + s], dmin, dmax);
-                const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
-                return (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
-            };
             float pf[NQ];
-            int o_next = 0;
-            if (s_begin < s_end) {
-                o_next = origin(s_begin);
+            {
+                const int o0 = s_org[wid][0];
                 const float* rr = res_frame + (int64_t)s_begin * p.T;
                 for (int q = 0; q < NQ; ++q) {
-                    const int k = o_next + q * 64 + lane;
+                    const int k = o0 + q * 64 + lane;
                     pf[q] = (k >= 0 && k < p.T) ? rr[k] : 0.f;
                 }
             }
-            for (int s = s_begin; s < s_end; ++s) {
-                const int o = o_next;
+            for (int j = 0; j < ns; ++j) {
+                const int o = s_org[wid][j];
                 wave_lds_sync();
                 for (int q = 0; q < NQ; ++q) row[q * 64 + lane] = pf[q];
                 wave_lds_sync();
-                if (s + 1 < s_end) {            // fetch the next sensor's row
-                    o_next = origin(s + 1);
-                    const float* rr = res_frame + (int64_t)(s + 1) * p.T;
+                if (j + 1 < ns) {               // fetch the next sensor's row
+                    const int on = s_org[wid][j + 1];
+                    const float* rr = res_frame + (int64_t)(s_begin + j + 1) * p.T;
                     for (int q = 0; q < NQ; ++q) {
-                        const int k = o_next + q * 64 + lane;
+                        const int k = on + q * 64 + lane;
                         pf[q] = (k >= 0 && k < p.T) ? rr[k] : 0.f;
                     }
                 }
-                if (!live) continue;
-                const double sx = p.sensors[s], sy = p.sensors[p.S + s], sz = p.sensors[2 * p.S + s];
-                const double dx = bl.x - sx, dy = bl.y - sy, dz = bl.z - sz;
-                const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, dx, dy, dz);
-                if (!w.ok) {
-                    raise_flag(p.flags, SB_FLAG_GEOMETRY);
-                    continue;
+                const double dx = bl.x - (double)s_sx[wid][j];
+                const double dy = bl.y - (double)s_sy[wid][j];
+                const double dz = bl.z - (double)s_sz[wid][j];
+                const double r = dist64(dx, dy, dz);
+                const double tau = fma(r, p.inv_delta, -p.t0fs);
+                const double kl = floor(tau - h_half);
+                const double a0d = tau - kl + 0.5;
+                const bool geo = w_ok && r > r_in;
+                if (w_ok && !(r > r_in)) raise_flag(p.flags, SB_FLAG_GEOMETRY);
+                const bool use = geo && fabs(kl) < 5.0e8;
+                const int klo = use ? (int)kl : 0;
+                const int tl = klo - o;
+                const bool in_row = tl >= 0 && tl + W <= UROW;
+                const float* rres = res_frame + (int64_t)(s_begin + j) * p.T;
+                float A = 0.f, Bs = 0.f, Cs = 0.f;
+                if (use) {
+                    float x = (float)a0d;
+                    if (KERNEL == SB_KERNEL_UNIFORM) {
+                        // inside boundaries m = 1..m_hi (m_hi decided in FP64); the loop runs a
+                        // wave-uniform count, later boundaries are masked (dr = 0)
+                        const int m_hi = (int)ceil(a0d + bl.rho) - 1;
+                        float r0, rp, sw = 0.f, st = 0.f;
+                        if (in_row) {
+                            const float* rw = row + tl;          // samples 0..W-1 lie in the row
+                            r0 = rw[0];
+                            rp = r0;
+                            for (int m = 1; m <= n_it; m += 4) {
+                                float v[4];
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) v[u] = rw[min(m + u, W - 1)];
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) {
+                                    x -= 1.f;
+                                    const float rm = (m + u <= m_hi) ? v[u] : rp;
+                                    const float dr = rm - rp;
+                                    rp = rm;
+                                    sw = fmaf(x * x, dr, sw);
+                                    st = fmaf(x, dr, st);
+                                }
+                            }
+                        } else {
+                            r0 = (klo >= 0 && klo < p.T) ? rres[klo] : 0.f;
+                            rp = r0;
+                            for (int m = 1; m <= m_hi; ++m) {
+                                x -= 1.f;
+                                const int k = klo + m;
+                                const float rm = (k >= 0 && k < p.T) ? rres[k] : 0.f;
+                                const float dr = rm - rp;
+                                rp = rm;
+                                sw = fmaf(x * x, dr, sw);
+                                st = fmaf(x, dr, st);
+                            }
+                        }
+                        Cs = rp - r0;
+                        A = fmaf(-rho * rho, Cs, sw);
+                        Bs = st;
+                    } else {
+                        // every boundary m = 0..W (r_{-1} = r_W = 0)
+                        const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale
+                        float rp = 0.f;
+                        for (int m = 0; m <= W; ++m) {
+                            const int k = klo + m;
+                            float rm = 0.f;
+                            if (m < W) rm = in_row ? row[tl + m] : ((k >= 0 && k < p.T) ? rres[k] : 0.f);
+                            const float dr = rm - rp;
+                            rp = rm;
+                            const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
+                            A += e;
+                            Bs = fmaf(x, e, Bs);
+                            Cs = fmaf(x * x, e, Cs);
+                            x -= 1.f;
+                        }
+                    }
                 }
-                if (!w.in_range) continue;      // the window reads only zeros
-                const float rho = bl.rhof;
-                const int tl = w.klo - o;
-                float A, Bs, Cs;
-                if (tl >= 0 && tl + w.W <= UROW) {
-                    const float* rw = row + tl;
-                    gather_window<KERNEL>(w, rho, [&](int m) { return rw[m]; }, A, Bs, Cs);
-                } else {
-                    const float* rr = res_frame + (int64_t)s * p.T;
-                    const int klo = w.klo, T = p.T;
-                    gather_window<KERNEL>(
-                        w, rho, [&](int m) { const int k = klo + m; return (k >= 0 && k < T) ? rr[k] : 0.f; },
-                        A, Bs, Cs);
+                if (use) {
+                    const float rf = (float)r;
+                    const float inv_r = __builtin_amdgcn_rcpf(rf);
+                    float dLdr, dLdR, dLdP;
+                    if (KERNEL == SB_KERNEL_UNIFORM) {
+                        const float Cr = delta * 0.25f * inv_r;   // C / P_f
+                        const float C = bl.amp * Cr;
+                        dLdr = 2.f * C * Bs * inv_delta_f - C * A * inv_r;
+                        dLdR = -2.f * rho * C * Cs * inv_delta_f;
+                        dLdP = Cr * A;
+                    } else {
+                        const float Kr = rho * rho * delta * 0.5f * inv_r;   // K / P_f
+                        const float K = bl.amp * Kr;
+                        dLdr = K / (rho * rho) * Bs * inv_delta_f + K * A * inv_r;
+                        dLdR = (-2.f * K / rho * A - K / (rho * rho * rho) * Cs) * inv_delta_f;
+                        dLdP = -Kr * A;
+                    }
+                    g5[0] = fmaf(dLdr, (float)dx * inv_r, g5[0]);
+                    g5[1] = fmaf(dLdr, (float)dy * inv_r, g5[1]);
+                    g5[2] = fmaf(dLdr, (float)dz * inv_r, g5[2]);
+                    g5[3] += dLdR;
+                    g5[4] += dLdP;
                 }
-                const float rf = (float)w.r;
-                const float inv_r = __builtin_amdgcn_rcpf(rf);
-                float dLdr, dLdR, dLdP;
-                if (KERNEL == SB_KERNEL_UNIFORM) {
-                    const float Cr = delta * 0.25f * inv_r;   // C / P_f
-                    const float C = bl.amp * Cr;
-                    const float Gv = C * A, Gt = 2.f * C * Bs, Gr = -2.f * rho * C * Cs;
-                    dLdr = Gt * inv_delta_f - Gv * inv_r;
-                    dLdR = Gr * inv_delta_f;
-                    dLdP = Cr * A;
-                } else {
-                    const float Kr = rho * rho * delta * 0.5f * inv_r;   // K / P_f
-                    const float K = bl.amp * Kr;
-                    const float Gv = -K * A;
-                    const float Gt = K / (rho * rho) * Bs;
-                    const float Ga = -2.f * K / rho * A - K / (rho * rho * rho) * Cs;
-                    dLdr = Gt * inv_delta_f - Gv * inv_r;
-                    dLdR = Ga * inv_delta_f;
-                    dLdP = -Kr * A;
-                }
-                g5[0] = fmaf(dLdr, (float)dx * inv_r, g5[0]);
-                g5[1] = fmaf(dLdr, (float)dy * inv_r, g5[1]);
-                g5[2] = fmaf(dLdr, (float)dz * inv_r, g5[2]);
-                g5[3] += dLdR;
-                g5[4] += dLdP;
             }
             // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame
             if (live) {
-                double fb[2 * SB_MAX_FOURIER];
-                if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
                 float base[5];
                 for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
                 for (int a = 0; a < 5; ++a) {
                     const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
-                    const float h = (float)eval_H(p, b, a, t, fb);
-                    gb[a] += additive ? g5[a] : g5[a] * (1.f + h);
+                    const float hh = (float)eval_H(p, b, a, t, fb);
+                    gb[a] += additive ? g5[a] : g5[a] * (1.f + hh);
                     const float gs = additive ? g5[a] : g5[a] * base[a];
                     if (MREG > 0) {
                         for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)fb[m], gd[a][m]);
@@ -254,24 +286,29 @@ __global__ __launch_bounds__(256) void adjoint_kernel(OpParams p) {
     }
 }
 
-template <int UROW, int KERNEL, int MREG>
+template <int UROW, int KERNEL, int MREG, int OCC>
 static hipError_t launch_adj_t(const OpParams& p, hipStream_t st) {
     int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((adjoint_kernel<UROW, KERNEL, MREG>), dim3((unsigned)grid), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((adjoint_kernel<UROW, KERNEL, MREG, OCC>), dim3((unsigned)grid), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
+template <int UROW, int KERNEL, int OCC>
+static hipError_t launch_adj_m(const OpParams& p, hipStream_t st) {
     // register accumulators for the Fourier coefficients when they fit (K <= 2)
     const bool reg = p.basis == SB_BASIS_FOURIER && p.M == 4;
-    if (tc.ucap == 128) {
-        if (kernel == SB_KERNEL_UNIFORM)
-            return reg ? launch_adj_t<128, 0, 4>(p, st) : launch_adj_t<128, 0, 0>(p, st);
-        return reg ? launch_adj_t<128, 1, 4>(p, st) : launch_adj_t<128, 1, 0>(p, st);
+    return reg ? launch_adj_t<UROW, KERNEL, 4, OCC>(p, st) : launch_adj_t<UROW, KERNEL, 0, OCC>(p, st);
+}
+
+// tc.ucap: residual row length; tc.nw: blocks per CU requested from the compiler (occupancy)
+hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
+    if (kernel == SB_KERNEL_UNIFORM && tc.ucap == 128) {
+        if (tc.nw == 2) return launch_adj_m<128, 0, 2>(p, st);
+        if (tc.nw == 3) return launch_adj_m<128, 0, 3>(p, st);
+        if (tc.nw == 4) return launch_adj_m<128, 0, 4>(p, st);
     }
-    if (tc.ucap == 192 && kernel == SB_KERNEL_GAUSS)
-        return reg ? launch_adj_t<192, 1, 4>(p, st) : launch_adj_t<192, 1, 0>(p, st);
+    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 192 && tc.nw == 2) return launch_adj_m<192, 1, 2>(p, st);
     return hipErrorInvalidValue;
 }
 

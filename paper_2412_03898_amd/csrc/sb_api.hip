@@ -114,21 +114,27 @@ static int validate_batch(const sb_batch* batch, Shape& sh) {
     return SB_OK;
 }
 
-// Tile configurations.  Forward: 4 waves x 64 sensors per block, chunks of 256
-// balls, 128-sample columns.  Adjoint: 128-sample residual rows (192 for the
-// Gaussian ball, whose windows are wider).
+// Tuning knobs (slingbag_tune): forward column length, adjoint occupancy target
+// and adjoint item count.  They change speed, not results (beyond the order of
+// floating-point atomics).
+struct Tuning {
+    int fwd_ucap = 128;        // 64 or 128 samples per LDS column
+    int adj_occ = 2;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
+    int adj_items = 4096;      // adjoint items the sensor split aims for
+};
+static Tuning g_tune;
+
 static TileCfg pick_forward_tiles(int kernel) {
     TileCfg tc;
     tc.nw = 4;
     tc.g = 256;
-    tc.ucap = 128;
-    (void)kernel;
+    tc.ucap = kernel == SB_KERNEL_UNIFORM ? g_tune.fwd_ucap : 128;
     return tc;
 }
 
 static TileCfg pick_adjoint_tiles(int kernel) {
     TileCfg tc;
-    tc.nw = 4;
+    tc.nw = kernel == SB_KERNEL_UNIFORM ? g_tune.adj_occ : 2;
     tc.g = 256;
     tc.ucap = kernel == SB_KERNEL_UNIFORM ? 128 : 192;
     return tc;
@@ -171,6 +177,8 @@ static void fill_forward(OpParams& p, const sb_config* cfg, const sb_batch* batc
     p.n_items = items;
 }
 
+constexpr int64_t kAdjMaxSplitHost = 256;   // sensors per adjoint item at most (LDS staging)
+
 // Adjoint items: (scene, chunk of 256 balls, split of the sensors); frames inside.
 // The sensors are split so that there are enough items to fill the chip.
 static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh) {
@@ -181,10 +189,12 @@ static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batc
         s.n_groups = (s.n_balls + 255) / 256;
         if (s.n_frames > 0) chunks += s.n_groups;
     }
-    const int64_t target = 4096;
+    const int64_t target = g_tune.adj_items;
     int64_t n_split = chunks > 0 ? (target + chunks - 1) / chunks : 1;
     const int64_t max_split = sh.S >= 8 ? sh.S / 8 : 1;
     if (n_split > max_split) n_split = max_split;
+    const int64_t min_split = (sh.S + kAdjMaxSplitHost - 1) / kAdjMaxSplitHost;   // kernel's LDS bound
+    if (n_split < min_split) n_split = min_split;
     if (n_split < 1) n_split = 1;
     p.s_per_split = (int32_t)((sh.S + n_split - 1) / n_split);
     p.n_sblocks = (int32_t)((sh.S + p.s_per_split - 1) / p.s_per_split);
@@ -219,8 +229,30 @@ static void time_mark(int kind, int which, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_mu);
     int slot = g_timing.used[kind];
     if (slot >= kTimingSlots) return;
-    hipEventRecord(g_timing.ev[kind][2 * slot + which], st);
+    (void)hipEventRecord(g_timing.ev[kind][2 * slot + which], st);
     if (which == 1) g_timing.used[kind] = slot + 1;
+}
+
+// Times `fn` (one launch sequence on stream s) `reps` times after one warm-up run.
+template <typename Fn>
+static int time_ms(hipStream_t s, int reps, Fn fn, float* ms_out) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    int st = fn();
+    if (st == SB_OK) {
+        (void)hipEventRecord(a, s);
+        for (int i = 0; i < reps && st == SB_OK; ++i) st = fn();
+        (void)hipEventRecord(b, s);
+        e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms_out, a, b);
+        if (e != hipSuccess && st == SB_OK) st = hip_fail(e, "autotune timing");
+        *ms_out /= (float)reps;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
 }
 
 }  // namespace sb
@@ -395,6 +427,82 @@ int slingbag_permute(const float* src, float* dst, int64_t rows, int64_t n, cons
     return SB_OK;
 }
 
+int slingbag_tune(int key, int value) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    switch (key) {
+        case SB_TUNE_FWD_COLUMN:
+            if (value != 64 && value != 128) return fail(SB_ERR_INVALID_ARG, "forward column must be 64 or 128");
+            g_tune.fwd_ucap = value;
+            return SB_OK;
+        case SB_TUNE_ADJ_OCCUPANCY:
+            if (value < 2 || value > 4) return fail(SB_ERR_INVALID_ARG, "adjoint occupancy must be 2..4");
+            g_tune.adj_occ = value;
+            return SB_OK;
+        case SB_TUNE_ADJ_ITEMS:
+            if (value < 1 || value > (1 << 22)) return fail(SB_ERR_INVALID_ARG, "adjoint items out of range");
+            g_tune.adj_items = value;
+            return SB_OK;
+        default:
+            return fail(SB_ERR_INVALID_ARG, "unknown tuning key %d", key);
+    }
+}
+
+int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* balls,
+                      const float* deform, const float* frame_t, const float* sensors, float* signals,
+                      float* grad_balls, float* grad_deform, int32_t* choice, void* stream) {
+    Shape sh;
+    int st = validate_config(cfg, sh);
+    if (st) return st;
+    if ((st = validate_batch(batch, sh))) return st;
+    if (!choice) return fail(SB_ERR_INVALID_ARG, "choice is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int reps = 2;
+    const Tuning saved = g_tune;
+    float best = 3.0e38f, ms = 0.f;
+    int best_col = g_tune.fwd_ucap;
+    for (int col : {64, 128}) {
+        if (cfg->kernel != SB_KERNEL_UNIFORM && col != 128) continue;
+        g_tune.fwd_ucap = col;
+        st = time_ms(s, reps, [&] { return slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream); }, &ms);
+        if (st) { g_tune = saved; return st; }
+        if (ms < best) { best = ms; best_col = col; }
+    }
+    g_tune.fwd_ucap = best_col;
+    // the forward output serves as a finite residual for timing the adjoint
+    st = slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream);
+    if (st) { g_tune = saved; return st; }
+    best = 3.0e38f;
+    int best_occ = g_tune.adj_occ, best_items = g_tune.adj_items;
+    for (int occ : {2, 3, 4}) {
+        for (int items : {2048, 4096, 8192}) {
+            if (cfg->kernel != SB_KERNEL_UNIFORM && occ != 2) continue;
+            g_tune.adj_occ = occ;
+            g_tune.adj_items = items;
+            st = time_ms(s, reps, [&] { return slingbag_adjoint(cfg, batch, balls, deform, frame_t, sensors, signals,
+                                                                 grad_balls, grad_deform, stream); }, &ms);
+            if (st) { g_tune = saved; return st; }
+            if (ms < best) { best = ms; best_occ = occ; best_items = items; }
+        }
+    }
+    g_tune.adj_occ = best_occ;
+    g_tune.adj_items = best_items;
+    choice[0] = best_col;
+    choice[1] = best_occ;
+    choice[2] = best_items;
+    return SB_OK;
+}
+
+int slingbag_tune_get(int key, int* value) {
+    if (!value) return fail(SB_ERR_INVALID_ARG, "value is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    switch (key) {
+        case SB_TUNE_FWD_COLUMN: *value = g_tune.fwd_ucap; return SB_OK;
+        case SB_TUNE_ADJ_OCCUPANCY: *value = g_tune.adj_occ; return SB_OK;
+        case SB_TUNE_ADJ_ITEMS: *value = g_tune.adj_items; return SB_OK;
+        default: return fail(SB_ERR_INVALID_ARG, "unknown tuning key %d", key);
+    }
+}
+
 int slingbag_timing(int enable) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -402,7 +510,7 @@ int slingbag_timing(int enable) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (enable && g_timing.device != dev) {
         for (int k = 0; k < kTimeKinds; ++k) {
-            for (hipEvent_t ev : g_timing.ev[k]) hipEventDestroy(ev);
+            for (hipEvent_t ev : g_timing.ev[k]) (void)hipEventDestroy(ev);
             g_timing.ev[k].assign(2 * kTimingSlots, nullptr);
             for (auto& ev : g_timing.ev[k]) {
                 e = hipEventCreate(&ev);

@@ -117,6 +117,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
     __shared__ int wave_cnt[NW];
     __shared__ float sred[NW][2];
     __shared__ int s_nsub, s_level;
+    __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
     __shared__ float tile[NW][UCAP][64];
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
@@ -133,8 +134,9 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         __syncthreads();   // the previous item is done with sball/scell/sub_start
 
         // ---- stage the chunk: deformed balls, grid cells, size and displacement bounds
-        double fb[2 * SB_MAX_FOURIER];
-        if (p.basis == SB_BASIS_FOURIER) fourier_basis(t, p.n_terms, fb);
+        if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
+        __syncthreads();
+        const double* fb = s_fb;
         float rho_max = 0.f, disp_max = 0.f;
         for (int i = tid; i < G; i += 64 * NW) {
             BallF bl;
@@ -183,15 +185,27 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             s_level = level;
         }
         __syncthreads();
-        // ---- sub-groups: runs of equal cell at the chosen level (block-wide compaction)
+        // ---- sub-groups: runs of equal cell at the chosen level (block-wide compaction).
+        // A ball whose cell differs from both neighbours while they agree (a ball
+        // that drifted just across a cell face since the balls were ordered) stays
+        // in the surrounding run; the run's bounding box, not its cell, sizes the
+        // columns, so this only keeps runs long.
         {
             const int level = s_level;
             const int i = tid;                 // G == 64 * NW (one ball per thread)
+            auto same = [&](int u, int v) {
+                return ((scell[u][0] >> level) == (scell[v][0] >> level)) &&
+                       ((scell[u][1] >> level) == (scell[v][1] >> level)) &&
+                       ((scell[u][2] >> level) == (scell[v][2] >> level));
+            };
             bool flag = false;
             if (i < nb) {
-                flag = (i == 0) || ((scell[i][0] >> level) != (scell[i - 1][0] >> level)) ||
-                       ((scell[i][1] >> level) != (scell[i - 1][1] >> level)) ||
-                       ((scell[i][2] >> level) != (scell[i - 1][2] >> level));
+                flag = (i == 0) || !same(i, i - 1);
+                if (flag && i > 0) {
+                    const bool intruder = i + 1 < nb && same(i - 1, i + 1);
+                    const bool after_intruder = i >= 2 && !same(i - 1, i - 2) && same(i - 2, i);
+                    if (intruder || after_intruder) flag = false;
+                }
             }
             const unsigned long long m = __ballot(flag);
             const int before = __popcll(m & ((1ull << lane) - 1ull));

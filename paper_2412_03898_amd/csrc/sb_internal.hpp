@@ -104,6 +104,17 @@ __device__ inline void fourier_basis(float t, int K, double* fb) {
     }
 }
 
+// Same values computed cooperatively: lane k < 2K of the calling wave writes entry
+// k of an LDS array (the values are the same for every lane of a frame).
+__device__ inline void fourier_basis_lanes(float t, int K, double* fb, int lane) {
+    if (lane < 2 * K) {
+        const int k = lane / 2 + 1;
+        double s, c;
+        sincospi(2.0 * k * (double)t, &s, &c);
+        fb[lane] = (lane & 1) ? s : c;
+    }
+}
+
 // H of attribute a of ball b at time t (Eq. 2 or the Fourier series), in FP64 so
 // that deformed positions and sizes carry no FP32 rounding into the arrival time.
 __device__ inline double eval_H(const OpParams& p, int64_t b, int a, float t, const double* fb) {

@@ -119,3 +119,30 @@ def test_header_constants_match_binding():
         m = re.search(rf"#define\s+{name}\s+\(?(-?\d+)\)?", text)
         assert m, name
         assert int(m.group(1)) == getattr(binding, name), name
+
+
+def test_tuning_knobs_validate_and_round_trip():
+    lib = binding.load()
+    assert lib.slingbag_tune(99, 1) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 96) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_tune(binding.SB_TUNE_ADJ_OCCUPANCY, 5) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_tune(binding.SB_TUNE_ADJ_ITEMS, 0) == binding.SB_ERR_INVALID_ARG
+    saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
+    try:
+        binding.tune(binding.SB_TUNE_FWD_COLUMN, 64)
+        binding.tune(binding.SB_TUNE_ADJ_OCCUPANCY, 3)
+        binding.tune(binding.SB_TUNE_ADJ_ITEMS, 1234)
+        assert (binding.tune_get(1), binding.tune_get(2), binding.tune_get(3)) == (64, 3, 1234)
+    finally:
+        for k, v in saved.items():
+            binding.tune(k, v)
+
+
+def test_order_and_permute_validation():
+    lib = binding.load()
+    b = _batch()
+    assert lib.slingbag_order(ctypes.byref(b), None, None, None) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_permute(None, None, 1, 4, None, None) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_permute(None, None, -1, 4, None, None) == binding.SB_ERR_SHAPE
+    assert lib.slingbag_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) \
+        == binding.SB_ERR_INVALID_ARG

@@ -301,3 +301,45 @@ def test_result_independent_of_order():
     perm = synth.morton_order(wl.balls)
     assert rel_l2(g1[0], g0[0][:, perm]) <= 1e-5
     assert rel_l2(g1[1], g0[1][:, :, perm]) <= 1e-5
+
+
+def test_autotune_then_parity():
+    """The autotuner picks a candidate setting and the tuned kernels still match the oracle."""
+    import torch
+    from paper_2412_03898_amd import binding, ops, tune
+    wl = synth.apply_order(synth.workload_vessel_4d(n_balls=3000, n_sensors=70, n_frames=4))
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
+    try:
+        choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
+        assert choice[0] in (64, 128) and choice[1] in (2, 3, 4) and choice[2] in (2048, 4096, 8192)
+        y = ops.forward(pb, balls, deform, ft, sens)
+        ops.check()
+        ref = oracle.forward(wl)
+        assert rel_l2(y.cpu().numpy(), ref) <= SIG_TOL
+        rng = np.random.default_rng(9)
+        res = rng.normal(size=ref.shape).astype(np.float32)
+        assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+    finally:
+        for k, v in saved.items():
+            binding.tune(k, v)
+
+
+@pytest.mark.parametrize("col,occ", [(64, 2), (64, 4), (128, 3), (128, 4)])
+def test_every_knob_setting_matches_oracle(col, occ):
+    """Every kernel instance the tuner can pick gives oracle-parity results."""
+    from paper_2412_03898_amd import binding
+    wl = synth.apply_order(synth.workload_vessel_static(n_balls=6000, n_sensors=130, n_samples=4096))
+    saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
+    try:
+        binding.tune(binding.SB_TUNE_FWD_COLUMN, col)
+        binding.tune(binding.SB_TUNE_ADJ_OCCUPANCY, occ)
+        y, flags = gpu_forward(wl)
+        ref = oracle.forward(wl)
+        assert rel_l2(y, ref) <= SIG_TOL
+        rng = np.random.default_rng(10)
+        res = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
+        assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+    finally:
+        for k, v in saved.items():
+            binding.tune(k, v)

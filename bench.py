@@ -77,6 +77,118 @@ def flop_model(wl):
     return {"forward": fwd, "adjoint": adj, "pairs": pairs, "mean_window": sumW / max(pairs, 1)}
 
 
+def _fourier_frames(wl, balls_np, deform_np):
+    """Per-frame static scenes of a Fourier-deformed scene (Eq. 1 with the Fourier
+    series; additive position), materialised in FP64 and stored as FP32: the input of
+    the frame-by-frame comparison path."""
+    import numpy as np
+    out = []
+    b = balls_np.astype(np.float64)
+    D = deform_np.astype(np.float64)
+    for f in range(wl.n_frames):
+        t = float(wl.frame_t[f])
+        h = sum(D[:, 2 * (k - 1)] * np.cos(2 * np.pi * k * t) + D[:, 2 * (k - 1) + 1] * np.sin(2 * np.pi * k * t)
+                for k in range(1, wl.n_terms + 1))
+        x = b.copy()
+        x[0:3] += h[0:3]
+        x[3:5] *= 1.0 + h[3:5]
+        out.append(np.ascontiguousarray(x.astype(np.float32)))
+    return out
+
+
+def ir_4d_comparison(steps, warmup):
+    """ms per IR iteration on the 4D vessel scene (50,000 balls, 16 frames, 512 sensors,
+    2,048 samples): all frames batched in one forward and one adjoint launch (25 parameters
+    per ball), against the frame-by-frame path (16 independent static scenes, one forward,
+    loss, adjoint and Adam each per iteration), with the peak device memory of each."""
+    import numpy as np
+    import torch
+    from paper_2412_03898_amd import ops, synth, tune
+    from paper_2412_03898_amd.binding import Problem
+
+    wl = synth.workload_vessel_4d()
+    pb, balls, deform, ft, sens = ops.to_device(wl, "cuda:0")
+    balls, deform, _ = ops.apply_order(pb, balls, deform)
+    choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
+    pert = torch.from_numpy(synth.perturbed(balls.cpu().numpy(), 1)).cuda()
+    pert, pert_def, _ = ops.apply_order(pb, pert, deform)
+    d = ops.forward(pb, pert, pert_def, ft, sens)
+    del pert, pert_def
+
+    def run(step_fn):
+        for _ in range(warmup):
+            step_fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            step_fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps * 1e3
+
+    # batched 4D step
+    torch.cuda.reset_peak_memory_stats()
+    y = torch.empty_like(d)
+    r = torch.empty_like(d)
+    L = torch.empty((), dtype=torch.float64, device="cuda")
+    gb = torch.empty_like(balls)
+    gd = torch.empty_like(deform)
+    groups = [(balls[0:3], gb[0:3], LR_POS), (balls[3], gb[3], LR_R), (balls[4], gb[4], LR_P), (deform, gd, LR_DEF)]
+    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in groups]
+    it = [0]
+
+    def batched():
+        ops.forward(pb, balls, deform, ft, sens, out=y)
+        ops.loss(pb, y, d, residual=r, loss_out=L)
+        ops.adjoint(pb, balls, deform, ft, sens, r, grad_balls=gb, grad_deform=gd)
+        it[0] += 1
+        for (p, g, lr), (m, v) in zip(groups, state):
+            ops.adam_(p, g, m, v, lr, it[0])
+
+    ms_batched = run(batched)
+    mem_batched = torch.cuda.max_memory_allocated() / 2**20
+    ops.check()
+    del y, r, gb, gd, state
+
+    # frame-by-frame path: each frame is its own static scene
+    frames_np = _fourier_frames(wl, balls.cpu().numpy(), deform.cpu().numpy())
+    B = wl.n_balls
+    pf = Problem(wl.kernel, 0, 0, 0, wl.n_sensors, wl.n_samples, wl.c, wl.fs, wl.t0,
+                 np.array([0, B]), np.array([0, 1]))
+    t0 = torch.zeros(1, dtype=torch.float32, device="cuda")
+    torch.cuda.reset_peak_memory_stats()
+    fb = [torch.from_numpy(x).cuda() for x in frames_np]
+    fy = torch.empty((1, wl.n_sensors, wl.n_samples), dtype=torch.float32, device="cuda")
+    fr = torch.empty_like(fy)
+    fL = torch.empty((), dtype=torch.float64, device="cuda")
+    fg = [torch.empty_like(x) for x in fb]
+    fstate = [[(torch.zeros_like(x[0:3]), torch.zeros_like(x[0:3])), (torch.zeros_like(x[3]), torch.zeros_like(x[3])),
+               (torch.zeros_like(x[4]), torch.zeros_like(x[4]))] for x in fb]
+    fit = [0]
+
+    def per_frame():
+        fit[0] += 1
+        for f in range(wl.n_frames):
+            ops.forward(pf, fb[f], None, t0, sens, out=fy)
+            ops.loss(pf, fy, d[f:f + 1], residual=fr, loss_out=fL)
+            ops.adjoint(pf, fb[f], None, t0, sens, fr, grad_balls=fg[f])
+            x, g = fb[f], fg[f]
+            for (p, gg, lr), (m, v) in zip(((x[0:3], g[0:3], LR_POS), (x[3], g[3], LR_R), (x[4], g[4], LR_P)),
+                                           fstate[f]):
+                ops.adam_(p, gg, m, v, lr, fit[0])
+
+    ms_frames = run(per_frame)
+    mem_frames = torch.cuda.max_memory_allocated() / 2**20
+    ops.check()
+    pairs = pb.pairs()
+    return {"workload": wl.name, "balls": wl.n_balls, "frames": wl.n_frames, "sensors": wl.n_sensors,
+            "samples": wl.n_samples, "tuning": list(choice),
+            "batched_ms_per_iter": round(ms_batched, 3), "per_frame_ms_per_iter": round(ms_frames, 3),
+            "speedup": round(ms_frames / ms_batched, 3),
+            "batched_gpairs_s": round(pairs / ms_batched / 1e6, 3),
+            "per_frame_gpairs_s": round(pairs / ms_frames / 1e6, 3),
+            "peak_mem_mb_batched": round(mem_batched, 1), "peak_mem_mb_per_frame": round(mem_frames, 1)}
+
+
 def cpu_baseline(wl, d_np):
     """Time the FP64 oracle on the host: one forward, loss and adjoint of the same workload."""
     import numpy as np
@@ -104,6 +216,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="vessel-single-frame", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-4d", action="store_true", help="skip the 4D batched vs per-frame comparison")
+    ap.add_argument("--tuning", default=None,
+                    help="fix the kernel knobs as COLUMN,OCCUPANCY,ITEMS instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the operator has no multi-GPU path in this build "
@@ -122,11 +237,16 @@ def main():
     balls, deform, _ = ops.apply_order(pb, balls, deform)
     # kernel knobs for this shape (timed once, outside the measured steps)
     from paper_2412_03898_amd import tune
-    choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
+    if args.tuning:
+        choice = tuple(int(v) for v in args.tuning.split(","))
+        tune.apply(choice)
+    else:
+        choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
     torch.cuda.synchronize()
     # measured data: the operator applied to a perturbed copy of the scene
     pert = torch.from_numpy(synth.perturbed(balls.cpu().numpy(), 1)).cuda()
-    d = ops.forward(pb, pert, deform, ft, sens)
+    pert, pert_def, _ = ops.apply_order(pb, pert, deform)
+    d = ops.forward(pb, pert, pert_def, ft, sens)
     y = torch.empty_like(d)
     r = torch.empty_like(d)
     L = torch.empty((), dtype=torch.float64, device="cuda")
@@ -162,6 +282,30 @@ def main():
     binding.timing(False)
     flags = ops.check()
 
+    # the same step replayed as a captured graph (forward + loss + adjoint) + Adam
+    graph = ops.StepGraph(pb, balls, deform, ft, sens, d)
+    ggroups = [(balls[0:3], graph.grad_balls[0:3], LR_POS), (balls[3], graph.grad_balls[3], LR_R),
+               (balls[4], graph.grad_balls[4], LR_P)]
+    if deform is not None:
+        ggroups.append((deform, graph.grad_deform, LR_DEF))
+
+    def gstep():
+        graph.run()
+        step_no[0] += 1
+        for (p, g, lr), (m, v) in zip(ggroups, state):
+            ops.adam_(p, g, m, v, lr, step_no[0])
+
+    for _ in range(args.warmup):
+        gstep()
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(args.steps):
+        gstep()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - tg) / args.steps * 1e3
+    graph.close()
+    ops.check()
+
     pairs = pb.pairs()
     ms_step = elapsed / args.steps * 1e3
     value = pairs * args.steps / elapsed / 1e9
@@ -193,8 +337,11 @@ def main():
                      "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
                      "flop_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3)},
         "kernel_ms": {k: (round(v, 4) if v is not None else None) for k, v in per_kernel.items()},
+        "graph_ms_per_step": round(ms_graph, 4),
         "device_flags": flags,
     }
+    if not args.no_4d:
+        out["ir_4d"] = ir_4d_comparison(max(3, args.steps // 4), 2)
     if not args.no_cpu_baseline:
         # the oracle's timing does not depend on the measured values: zeros stand in for them
         d_np = np.zeros((wl.n_frames, wl.n_sensors, wl.n_samples))

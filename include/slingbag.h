@@ -180,6 +180,25 @@ int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n
  * SB_ERR_DEVICE_FLAG if SB_FLAG_GEOMETRY or SB_FLAG_NONFINITE was raised. */
 int slingbag_check(void* stream, uint32_t* flags);
 
+/* One IR step as a captured HIP graph (Sec. 2.2: forward, L2 loss and the
+ * gradient of every parameter, per iteration).  slingbag_plan_create records
+ * slingbag_forward, slingbag_loss (residual = signals - measured, *loss) and
+ * slingbag_adjoint (with that residual) on `stream` (must not be NULL) into a
+ * graph and instantiates it; slingbag_plan_run replays the whole sequence with
+ * one hipGraphLaunch on any stream.  The plan binds the buffers and the tuning
+ * knobs of its creation: the caller may change their contents (for instance
+ * update balls and deform in place between runs) but not their addresses or
+ * the shapes.  No memsets are recorded (outputs are cleared by kernels).  The
+ * plan owns only the graph; slingbag_plan_destroy releases it (NULL is a
+ * no-op). */
+typedef struct sb_plan sb_plan;
+int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const float* balls,
+                         const float* deform, const float* frame_t, const float* sensors,
+                         const float* measured, float* signals, float* residual, double* loss,
+                         float* grad_balls, float* grad_deform, void* stream, sb_plan** out);
+int slingbag_plan_run(sb_plan* plan, void* stream);
+int slingbag_plan_destroy(sb_plan* plan);
+
 /* Tuning knobs, read by every later call on any device (process-wide).  They
  * change speed only; results differ at most by the order of FP32 atomic
  * additions.  The autotuner (python: paper_2412_03898_amd.tune) times the

@@ -63,6 +63,10 @@ _SIGS = {
                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP],
     "slingbag_order": [ctypes.POINTER(Batch), _VP, _VP, _VP],
     "slingbag_permute": [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP],
+    "slingbag_plan_create": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP, _VP,
+                             _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_void_p)],
+    "slingbag_plan_run": [_VP, _VP],
+    "slingbag_plan_destroy": [_VP],
     "slingbag_tune": [ctypes.c_int, ctypes.c_int],
     "slingbag_autotune": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP, _VP,
                           _VP, ctypes.POINTER(ctypes.c_int32), _VP],
@@ -169,6 +173,24 @@ def adjoint(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, re
 def adam(param: int, grad: int, m: int, v: int, n: int, lr: float, beta1: float, beta2: float,
          eps: float, step: int, stream: int = 0):
     _check(load().slingbag_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, stream))
+
+
+def plan_create(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, measured: int,
+                signals: int, residual: int, loss_out: int, grad_balls: int, grad_deform: int,
+                stream: int) -> int:
+    h = ctypes.c_void_p(0)
+    _check(load().slingbag_plan_create(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), balls, deform, frame_t,
+                                       sensors, measured, signals, residual, loss_out, grad_balls,
+                                       grad_deform, stream, ctypes.byref(h)))
+    return int(h.value)
+
+
+def plan_run(plan: int, stream: int):
+    _check(load().slingbag_plan_run(plan, stream))
+
+
+def plan_destroy(plan: int):
+    _check(load().slingbag_plan_destroy(plan))
 
 
 def order(pb: Problem, balls: int, perm: int, stream: int = 0):

@@ -226,6 +226,8 @@ static Timing g_timing;
 
 static void time_mark(int kind, int which, hipStream_t st) {
     if (!g_timing.enabled) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_mu);
     int slot = g_timing.used[kind];
     if (slot >= kTimingSlots) return;
@@ -542,6 +544,70 @@ int slingbag_timing_read(double* total_ms, int64_t* launches) {
         launches[k] = n;
         if (g_timing.device >= 0) g_timing.used[k] = 0;
     }
+    return SB_OK;
+}
+
+struct sb_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = -1;
+};
+
+int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const float* balls,
+                         const float* deform, const float* frame_t, const float* sensors,
+                         const float* measured, float* signals, float* residual, double* loss,
+                         float* grad_balls, float* grad_deform, void* stream, sb_plan** out) {
+    if (!out) return fail(SB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Shape sh;
+    int st = validate_config(cfg, sh);
+    if (st) return st;
+    if ((st = validate_batch(batch, sh))) return st;
+    if (!stream) return fail(SB_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+    DeviceState* ds;
+    if ((st = device_state(&ds))) return st;   // per-device buffers exist before capture
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    st = slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream);
+    if (st == SB_OK) st = slingbag_loss(cfg, batch, signals, measured, residual, loss, stream);
+    if (st == SB_OK)
+        st = slingbag_adjoint(cfg, batch, balls, deform, frame_t, sensors, residual, grad_balls, grad_deform, stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (st != SB_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    sb_plan* plan = new sb_plan;
+    plan->graph = graph;
+    plan->exec = exec;
+    (void)hipGetDevice(&plan->device);
+    *out = plan;
+    return SB_OK;
+}
+
+int slingbag_plan_run(sb_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return fail(SB_ERR_INVALID_ARG, "plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SB_OK;
+}
+
+int slingbag_plan_destroy(sb_plan* plan) {
+    if (!plan) return SB_OK;
+    hipError_t e = hipSuccess;
+    if (plan->exec) e = hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
     return SB_OK;
 }
 

@@ -90,6 +90,50 @@ def adam_(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
     return param
 
 
+class StepGraph:
+    """forward + loss + adjoint captured once as a HIP graph (slingbag_plan_*), replayed per step.
+
+    Binds the given tensors: update their contents in place between runs (e.g. the
+    optimiser step), never reallocate them.  Needs a non-default stream (capture).
+    """
+
+    def __init__(self, pb: Problem, balls, deform, frame_t, sensors, measured, stream=None):
+        B, F, S, T, M = _shapes(pb)
+        dev = balls.device
+        self.pb = pb
+        self.tensors = (balls, deform, frame_t, sensors, measured)
+        self.signals = torch.empty((F, S, T), dtype=torch.float32, device=dev)
+        self.residual = torch.empty_like(self.signals)
+        self.loss = torch.empty((), dtype=torch.float64, device=dev)
+        self.grad_balls = torch.empty((5, B), dtype=torch.float32, device=dev)
+        self.grad_deform = torch.empty((5, M, B), dtype=torch.float32, device=dev) if M else None
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.handle = binding.plan_create(
+            pb, _ptr(balls, "balls", (5, B)), _ptr(deform, "deform", (5, M, B) if M else None),
+            _ptr(frame_t, "frame_t", (F,)), _ptr(sensors, "sensors", (3, S)),
+            _ptr(measured, "measured", (F, S, T)), _ptr(self.signals, "signals"),
+            _ptr(self.residual, "residual"), _ptr(self.loss, "loss", (), torch.float64),
+            _ptr(self.grad_balls, "grad_balls"),
+            _ptr(self.grad_deform, "grad_deform") if M else None, self.stream.cuda_stream)
+
+    def run(self):
+        """Replay on the current stream; returns (loss, grad_balls, grad_deform)."""
+        binding.plan_run(self.handle, torch.cuda.current_stream().cuda_stream)
+        return self.loss, self.grad_balls, self.grad_deform
+
+    def close(self):
+        if self.handle:
+            binding.plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def order(pb: Problem, balls):
     """Morton permutation of every scene's balls (slingbag_order): int32 [B] on the GPU."""
     B = pb.n_balls

@@ -1,0 +1,116 @@
+"""GPU: the torch.autograd wrapper and the captured-graph IR step, against the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_l2, with_
+from paper_2412_03898_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene():
+    return synth.apply_order(synth.workload_vessel_4d(n_balls=2500, n_sensors=70, n_frames=6))
+
+
+def test_autograd_gradient_matches_oracle():
+    import torch
+    from paper_2412_03898_amd import ops
+    from paper_2412_03898_amd.autograd import l2_loss, radiate
+    wl = _scene()
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    d_np = oracle.forward(wl, balls=synth.perturbed(wl.balls, 3)).astype(np.float32)
+    d = torch.from_numpy(d_np).cuda()
+    b = balls.clone().requires_grad_(True)
+    D = deform.clone().requires_grad_(True)
+    L = l2_loss(pb, radiate(pb, b, D, ft, sens), d)
+    L.backward()
+    y_ref = oracle.forward(wl)
+    L_ref, r_ref = oracle.loss(y_ref, d_np)
+    gb_ref, gd_ref = oracle.adjoint(wl, r_ref)
+    assert float(L.item()) == pytest.approx(L_ref, rel=2e-5)
+    g = b.grad.cpu().numpy()
+    assert rel_l2(g[0:3], gb_ref[0:3]) <= 1e-4
+    assert rel_l2(g[3], gb_ref[3]) <= 1e-4
+    assert rel_l2(g[4], gb_ref[4]) <= 1e-4
+    gd = D.grad.cpu().numpy()
+    for a in range(5):
+        assert rel_l2(gd[a], gd_ref[a]) <= 1e-4, a
+
+
+def test_autograd_matches_finite_differences_of_oracle_loss():
+    """<grad, v> from the GPU autograd gradient against central differences of the FP64
+    oracle loss, along random directions and for single deformation coefficients."""
+    import torch
+    from paper_2412_03898_amd import ops
+    from paper_2412_03898_amd.autograd import l2_loss, radiate
+    wl = _scene()
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    d_np = oracle.forward(wl, balls=synth.perturbed(wl.balls, 4)).astype(np.float32)
+    d = torch.from_numpy(d_np).cuda()
+    b = balls.clone().requires_grad_(True)
+    D = deform.clone().requires_grad_(True)
+    l2_loss(pb, radiate(pb, b, D, ft, sens), d).backward()
+    gb = b.grad.cpu().numpy().astype(np.float64)
+    gd = D.grad.cpu().numpy().astype(np.float64)
+    B0 = wl.balls.astype(np.float64)
+    D0 = wl.deform.astype(np.float64)
+
+    def L(bb, dd):
+        y = oracle.forward(wl, balls=bb, deform=dd)
+        return 0.5 * float(((y - d_np) ** 2).sum())
+
+    rng = np.random.default_rng(11)
+    for trial in range(2):
+        vb = rng.normal(size=B0.shape) * np.array([1e-6, 1e-6, 1e-6, 1e-6, 1e-3])[:, None]
+        vd = rng.normal(size=D0.shape) * np.array([1e-6, 1e-6, 1e-6, 1e-3, 1e-3])[:, None, None]
+        # steps of ~1e-12 m: small enough that no ball edge crosses a sample boundary inside
+        # the difference (the loss has kinks there), large enough for FP64
+        eps = 1e-6
+        fd = (L(B0 + eps * vb, D0 + eps * vd) - L(B0 - eps * vb, D0 - eps * vd)) / (2 * eps)
+        an = float((gb * vb).sum() + (gd * vd).sum())
+        assert an == pytest.approx(fd, rel=1e-4), trial
+    # single coefficients: the largest-gradient entries of the position and pressure groups
+    for a in (0, 4):
+        m, bi = np.unravel_index(np.argmax(np.abs(gd[a])), gd[a].shape)
+        e = 1e-12 if a < 3 else 1e-9
+        Dp, Dm = D0.copy(), D0.copy()
+        Dp[a, m, bi] += e
+        Dm[a, m, bi] -= e
+        fd = (L(B0, Dp) - L(B0, Dm)) / (2 * e)
+        assert gd[a, m, bi] == pytest.approx(fd, rel=1e-3), (a, m, bi)
+
+
+def test_graph_replays_match_eager():
+    """Replay the captured forward+loss+adjoint several times, with eager work (an in-place
+    parameter update) and synchronisations between replays; every replay equals the eager
+    sequence on the same inputs."""
+    import torch
+    from paper_2412_03898_amd import ops
+    wl = _scene()
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    d = torch.from_numpy(oracle.forward(wl, balls=synth.perturbed(wl.balls, 5)).astype(np.float32)).cuda()
+    g = ops.StepGraph(pb, balls, deform, ft, sens, d)
+    try:
+        for rep in range(4):
+            balls[0].add_(2e-6)            # eager work between replays, in place
+            deform[4].mul_(0.99)
+            torch.cuda.synchronize()
+            Lg, gbg, gdg = g.run()
+            torch.cuda.synchronize()
+            Lg, gbg, gdg, yg = float(Lg.item()), gbg.clone(), gdg.clone(), g.signals.clone()
+            y = ops.forward(pb, balls, deform, ft, sens)
+            L, r = ops.loss(pb, y, d)
+            gb, gd = ops.adjoint(pb, balls, deform, ft, sens, r)
+            torch.cuda.synchronize()
+            assert Lg == pytest.approx(float(L.item()), rel=1e-6), rep
+            assert rel_l2(yg.cpu().numpy(), y.cpu().numpy()) <= 1e-6, rep
+            assert rel_l2(gbg.cpu().numpy(), gb.cpu().numpy()) <= 1e-5, rep
+            assert rel_l2(gdg.cpu().numpy(), gd.cpu().numpy()) <= 1e-5, rep
+        ops.check()
+        # and the last replay against the oracle
+        wl2 = with_(wl, balls=balls.cpu().numpy(), deform=deform.cpu().numpy())
+        assert rel_l2(g.signals.cpu().numpy(), oracle.forward(wl2)) <= 1e-5
+    finally:
+        g.close()

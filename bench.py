@@ -217,6 +217,10 @@ def main():
     ap.add_argument("--workload", default="vessel-single-frame", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-4d", action="store_true", help="skip the 4D batched vs per-frame comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 1 GiB device-to-device copy (a known amount of HBM traffic for "
+                         "scaling memory counters)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph step timing")
     ap.add_argument("--tuning", default=None,
                     help="fix the kernel knobs as COLUMN,OCCUPANCY,ITEMS instead of autotuning")
     args = ap.parse_args()
@@ -283,28 +287,30 @@ def main():
     flags = ops.check()
 
     # the same step replayed as a captured graph (forward + loss + adjoint) + Adam
-    graph = ops.StepGraph(pb, balls, deform, ft, sens, d)
-    ggroups = [(balls[0:3], graph.grad_balls[0:3], LR_POS), (balls[3], graph.grad_balls[3], LR_R),
-               (balls[4], graph.grad_balls[4], LR_P)]
-    if deform is not None:
-        ggroups.append((deform, graph.grad_deform, LR_DEF))
+    ms_graph = None
+    graph = None if args.no_graph else ops.StepGraph(pb, balls, deform, ft, sens, d)
+    if graph is not None:
+        ggroups = [(balls[0:3], graph.grad_balls[0:3], LR_POS), (balls[3], graph.grad_balls[3], LR_R),
+                   (balls[4], graph.grad_balls[4], LR_P)]
+        if deform is not None:
+            ggroups.append((deform, graph.grad_deform, LR_DEF))
 
-    def gstep():
-        graph.run()
-        step_no[0] += 1
-        for (p, g, lr), (m, v) in zip(ggroups, state):
-            ops.adam_(p, g, m, v, lr, step_no[0])
+        def gstep():
+            graph.run()
+            step_no[0] += 1
+            for (p, g, lr), (m, v) in zip(ggroups, state):
+                ops.adam_(p, g, m, v, lr, step_no[0])
 
-    for _ in range(args.warmup):
-        gstep()
-    torch.cuda.synchronize()
-    tg = time.perf_counter()
-    for _ in range(args.steps):
-        gstep()
-    torch.cuda.synchronize()
-    ms_graph = (time.perf_counter() - tg) / args.steps * 1e3
-    graph.close()
-    ops.check()
+        for _ in range(args.warmup):
+            gstep()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            gstep()
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - tg) / args.steps * 1e3
+        graph.close()
+        ops.check()
 
     pairs = pb.pairs()
     ms_step = elapsed / args.steps * 1e3
@@ -337,7 +343,7 @@ def main():
                      "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
                      "flop_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3)},
         "kernel_ms": {k: (round(v, 4) if v is not None else None) for k, v in per_kernel.items()},
-        "graph_ms_per_step": round(ms_graph, 4),
+        "graph_ms_per_step": None if ms_graph is None else round(ms_graph, 4),
         "device_flags": flags,
     }
     if not args.no_4d:
@@ -348,6 +354,11 @@ def main():
         cb = cpu_baseline(wl, d_np)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -31,45 +31,73 @@
 
 namespace sb {
 
-template <int KERNEL>
-__device__ inline float trace_coef(const BallF& bl, double r, float delta) {
-    if (KERNEL == SB_KERNEL_UNIFORM) return (float)((double)bl.amp * (double)delta / (4.0 * r));
-    return (float)((double)bl.amp * bl.rho * bl.rho * (double)delta / (2.0 * r));
+// Add N consecutive values v0 - 2C*u (u = 0..N-1, a stretch of the ramp) to a
+// tile column: all N entries are read before any is written back, so the wave
+// waits for LDS once per stretch.
+template <int N>
+__device__ inline void add_ramp(float* cp, float yb, float m2c) {
+    float o[N];
+#pragma unroll
+    for (int u = 0; u < N; ++u) o[u] = cp[u * 64];
+#pragma unroll
+    for (int u = 0; u < N; ++u) cp[u * 64] = o[u] + fmaf(m2c, (float)u, yb);
 }
 
 // Add one ball's window (W samples from boundary x0 on) to a tile column
-// (stride 64 floats) or, when out of the tile, straight to the global row.
+// (stride 64 floats).  `C` is the per-pair amplitude (P_f delta / (4 r) for the
+// uniform sphere, P_f rho^2 delta / (2 r) for the Gaussian ball).
+//
+// Uniform sphere: with x0 in [rho, rho + 1) and W = floor(2 rho) + 2, boundaries
+// 1 .. W-2 lie inside [-rho, rho] and boundary W below -rho, so samples
+// 1 .. W-3 see both of their boundaries inside and equal C (x_j^2 - x_{j+1}^2)
+// = C (2 x_j - 1): a ramp falling by 2C per sample (the N-wave is linear in
+// time).  Sample 0 and the last two samples take the clamped form.
 template <int KERNEL>
-__device__ inline void add_window(float* c, int W, float x, float rho, float C) {
+__device__ inline void add_window(float* c, int W, float x0, float rho, float C) {
     if (KERNEL == SB_KERNEL_UNIFORM) {
-        float Qp = rho * rho;
-        int j = 0;
-        for (; j + 4 <= W; j += 4) {
-            float v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                x -= 1.f;
-                const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
-                const float Q = q * q;
-                v[u] = C * (Qp - Q);
-                Qp = Q;
-            }
-            float o[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) o[u] = c[(j + u) * 64];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) c[(j + u) * 64] = o[u] + v[u];
-        }
-        for (; j < W; ++j) {
-            x -= 1.f;
+        // sample 0 and the last two samples e1 = W-2, e2 = W-1 (for W = 2: samples
+        // 1 and 2, the latter zero; the caller keeps three rows in the tile)
+        const float rr = rho * rho;
+        auto sq = [&](float x) {
             const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
-            const float Q = q * q;
-            c[j * 64] += C * (Qp - Q);
-            Qp = Q;
+            return q * q;
+        };
+        const int e1 = max(W - 2, 1);
+        const float xa = x0 - (float)e1;                 // boundary e1 (exact in FP32)
+        const float qa = sq(xa), qb = sq(xa - 1.f);
+        {
+            float* const p1 = c + e1 * 64;
+            const float o0 = c[0], o1 = p1[0], o2 = p1[64];
+            c[0] = o0 + C * (rr - sq(x0 - 1.f));
+            p1[0] = o1 + C * (qa - qb);
+            p1[64] = o2 + C * (qb - rr);                 // boundary e1 + 2 lies below -rho
+        }
+        // interior samples 1 .. W-3: v_j = y - 2C j, y = C (2 x0 - 1)
+        const float m2c = -2.f * C;
+        float yb = fmaf(C, fmaf(2.f, x0, -1.f), m2c);   // v_1
+        float* cp = c + 64;
+        int n = W - 3;
+        for (; n >= 8; n -= 8) {
+            add_ramp<8>(cp, yb, m2c);
+            cp += 8 * 64;
+            yb = fmaf(m2c, 8.f, yb);
+        }
+        if (n > 0) {
+            if (n & 4) {
+                add_ramp<4>(cp, yb, m2c);
+                cp += 4 * 64;
+                yb = fmaf(m2c, 4.f, yb);
+            }
+            if (n & 2) {
+                add_ramp<2>(cp, yb, m2c);
+                cp += 2 * 64;
+                yb = fmaf(m2c, 2.f, yb);
+            }
+            if (n & 1) add_ramp<1>(cp, yb, m2c);
         }
     } else {
         const float ce = -1.f / (2.f * rho * rho);
-        float Ep = __expf(x * x * ce);
+        float Ep = __expf(x0 * x0 * ce), x = x0;
         for (int j = 0; j < W; ++j) {
             x -= 1.f;
             const float E = __expf(x * x * ce);
@@ -78,6 +106,17 @@ __device__ inline void add_window(float* c, int W, float x, float rho, float C) 
         }
     }
 }
+
+// Per-pair quantities of one ball for the wave's 64 sensors (one per lane).
+struct FwdPair {
+    float C, x0;     // amplitude and boundary 0 (zero in lanes that add nothing to the tile)
+    float Cg, xg;    // the same for the direct path to global memory
+    float rhof;
+    int tl;          // tile row of sample 0 (0 in lanes that add nothing to the tile)
+    int klo;         // sample index of sample 0
+    int W;           // window length (the same in every lane)
+    bool in_tile, glob;
+};
 
 template <int KERNEL>
 __device__ inline bool add_window_global(float* row, int klo, int T, int W, float x, float rho,
@@ -118,11 +157,11 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
     __shared__ float sred[NW][2];
     __shared__ int s_nsub, s_level;
     __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
-    __shared__ float tile[NW][UCAP][64];
+    __shared__ float tile[NW][(UCAP + 1) * 64];     // per wave: a pad row, then UCAP rows of 64 sensors
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-    float* const tw = &tile[wid][0][0];
-    for (int k = 0; k < UCAP; ++k) tw[k * 64 + lane] = 0.f;
+    float* const tw = &tile[wid][64];
+    for (int k = -1; k < UCAP; ++k) tw[k * 64 + lane] = 0.f;
 
     for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
         const Item it = decode_item(p, item);
@@ -144,6 +183,10 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             if (i < nb) {
                 const int64_t b = first + i;
                 if (!deform_ball(p, b, t, fb, bl)) raise_flag(p.flags, SB_FLAG_NONFINITE);
+                // amplitude scale of the trace: P_f delta / 4 (uniform), P_f rho^2 delta / 2 (Gaussian)
+                bl.amp = (KERNEL == SB_KERNEL_UNIFORM)
+                             ? (float)((double)bl.amp * (double)p.delta * 0.25)
+                             : (float)((double)bl.amp * bl.rho * bl.rho * (double)p.delta * 0.5);
                 const double bx = p.balls[b], by = p.balls[p.B + b], bz = p.balls[2 * p.B + b];
                 c3[0] = grid_coord(bx);
                 c3[1] = grid_coord(by);
@@ -164,8 +207,8 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             scell[i][1] = c3[1];
             scell[i][2] = c3[2];
         }
-        rho_max = wave_max(rho_max);
-        disp_max = wave_max(disp_max);
+        rho_max = wave_max_all(rho_max);   // every lane takes exactly one ball slot above
+        disp_max = wave_max_all(disp_max);
         if (lane == 0) { sred[wid][0] = rho_max; sred[wid][1] = disp_max; }
         __syncthreads();
         if (tid == 0) {
@@ -228,9 +271,9 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         const bool active = s < p.S;
         double sx = 0.0, sy = 0.0, sz = 0.0;
         if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
-        float* out_row = p.signals + ((int64_t)gf * p.S + (active ? s : 0)) * p.T;
-        const int64_t frame_base = (int64_t)gf * p.S * p.T;
-        bool clipped = false;
+        const int64_t row_off = ((int64_t)gf * p.S + (active ? s : 0)) * p.T;   // this lane's trace row
+        float* out_row = p.signals + row_off;
+        bool clipped = false, geometry = false;
 
         for (int sg = 0; sg < nsub; ++sg) {
             const int i0 = sub_start[sg], i1 = sub_start[sg + 1];
@@ -245,8 +288,8 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 lo[2] = fminf(lo[2], __double2float_rd(bl.z)); hi[2] = fmaxf(hi[2], __double2float_ru(bl.z));
                 rmax = fmaxf(rmax, bl.rhof);
             }
-            for (int a = 0; a < 3; ++a) { lo[a] = wave_min(lo[a]); hi[a] = wave_max(hi[a]); }
-            rmax = wave_max(rmax);
+            for (int a = 0; a < 3; ++a) { lo[a] = wave_min_all(lo[a]); hi[a] = wave_max_all(hi[a]); }
+            rmax = wave_max_all(rmax);
             if (!(lo[0] <= hi[0])) continue;          // no valid ball in this sub-group
             const double hmax = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rmax : (double)kGaussCut * rmax;
             double dmin, dmax;
@@ -256,59 +299,96 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             const int o = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
             int kmax = -1;
 
-            for (int i = i0; i < i1; ++i) {
+            // pair set-up of ball i for this wave's sensors; windows that do not fit
+            // the tile, invalid balls and inactive lanes add zeros at rows 0..2
+            auto prep = [&](int i) {
+                FwdPair f;
                 const BallF bl = sball[i];
-                if (bl.rho < 0.0 || !active) continue;
+                const bool valid = bl.rho >= 0.0;
+                const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
+                const bool too_long = valid && h >= 1.0e6;       // window longer than any record
+                const int Wb = (int)(2.0 * fmin(fmax(h, 0.0), 1.0e6)) + 2;
+                f.W = __builtin_amdgcn_readfirstlane(Wb);
                 const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, bl.x - sx, bl.y - sy, bl.z - sz);
-                if (!w.ok) {
-                    raise_flag(p.flags, SB_FLAG_GEOMETRY);
-                    continue;
-                }
-                if (!w.in_range) {          // arrival far outside any record: nothing to add
-                    clipped = true;
-                    continue;
-                }
-                const float C = trace_coef<KERNEL>(bl, w.r, p.delta);
+                const bool use = active && valid && !too_long;
+                geometry |= use && !w.ok;
+                clipped |= (active && too_long) || (use && w.ok && !w.in_range);
+                const bool part = use && w.ok && w.in_range;
                 const int tl = w.klo - o;
-                const float x0 = (float)w.a0;
-                if (tl >= 0 && tl + w.W <= UCAP) {
-                    add_window<KERNEL>(tw + tl * 64 + lane, w.W, x0, bl.rhof, C);
-                    kmax = max(kmax, tl + w.W - 1);
-                } else {
-                    clipped |= add_window_global<KERNEL>(out_row, w.klo, p.T, w.W, x0, bl.rhof, C);
+                const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
+                f.in_tile = part && tl >= 0 && tl + rows <= UCAP;
+                f.glob = part && !f.in_tile;
+                f.Cg = bl.amp * w.ri;                            // amp holds the amplitude scale (staging)
+                f.xg = (float)w.a0;
+                f.C = f.in_tile ? f.Cg : 0.f;
+                f.x0 = f.in_tile ? f.xg : 0.f;
+                f.tl = f.in_tile ? tl : 0;
+                f.klo = w.klo;
+                f.rhof = bl.rhof;
+                return f;
+            };
+            auto apply = [&](const FwdPair& f) {
+                const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
+                if (rows <= UCAP) add_window<KERNEL>(tw + f.tl * 64 + lane, f.W, f.x0, f.rhof, f.C);
+                if (f.in_tile) kmax = max(kmax, f.tl + f.W - 1);
+                if (__ballot(f.glob)) {
+                    if (f.glob) clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
                 }
+            };
+            // software pipeline: the set-up of ball i+1 overlaps the tile update of ball i
+            FwdPair cur = prep(i0);
+            for (int i = i0; i < i1; ++i) {
+                const FwdPair nxt = prep(min(i + 1, i1 - 1));
+                apply(cur);
+                cur = nxt;
             }
 
-            // ---- flush: transpose each touched 64-sample block in place, then one
-            // coalesced atomic per (sensor, block)
-            const int nblk = (wave_max_i(kmax) + 64) >> 6;
+            // ---- flush, per touched 64-sample block q: each lane reads its column
+            // (64 samples of its sensor) into registers and writes it back as row
+            // `lane` of a 64 x 65 matrix that starts 64 floats before the block
+            // (in the previous, already flushed block, or the pad row before the
+            // tile); the row stride of 65 keeps both the row writes and the column
+            // reads of the matrix conflict-free.  Row a then holds 64 consecutive
+            // samples of sensor a, added to the global trace with one coalesced FP32
+            // atomic per row.
+            const int nblk = (wave_max_all(kmax) + 64) >> 6;
             for (int q = 0; q < nblk; ++q) {
-                float* blk = tw + q * 64 * 64;
+                float* const blk = tw + q * 64 * 64;
+                float* const mat = blk - 64;
+                float col[64];
                 wave_lds_sync();
-                for (int d = 1; d <= 32; ++d) {
-                    if (d < 32 || lane < 32) {
-                        const int c = (lane + d) & 63;
-                        const float a = blk[lane * 64 + c];
-                        const float b = blk[c * 64 + lane];
-                        blk[lane * 64 + c] = b;
-                        blk[c * 64 + lane] = a;
+#pragma unroll
+                for (int k = 0; k < 64; ++k) col[k] = blk[k * 64 + lane];
+                wave_lds_sync();
+#pragma unroll
+                for (int k = 0; k < 64; ++k) mat[lane * 65 + k] = col[k];
+                wave_lds_sync();
+#pragma unroll
+                for (int a0 = 0; a0 < 64; a0 += 8) {
+                    float v[8];                                  // sample q*64 + lane of sensors a0 .. a0+7
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int a = a0 + u;
+                        const int act_a = __builtin_amdgcn_readlane((int)active, a);
+                        const int k = __builtin_amdgcn_readlane(o, a) + q * 64 + lane;
+                        const int64_t ra = ((int64_t)__builtin_amdgcn_readlane((int)(row_off >> 32), a) << 32) |
+                                           (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)row_off, a);
+                        if (v[u] != 0.f && act_a) {
+                            if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + ra + k, v[u]);
+                            else clipped = true;
+                        }
                     }
                 }
                 wave_lds_sync();
-                for (int a = 0; a < 64; ++a) {
-                    const float v = blk[a * 64 + lane];
-                    blk[a * 64 + lane] = 0.f;
-                    const int sa = __builtin_amdgcn_readlane(s, a);
-                    const int oa = __builtin_amdgcn_readlane(o, a);
-                    const int k = oa + q * 64 + lane;
-                    if (v != 0.f && sa < p.S) {
-                        if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + frame_base + (int64_t)sa * p.T + k, v);
-                        else clipped = true;
-                    }
-                }
+#pragma unroll
+                for (int k = 0; k < 64; ++k) blk[k * 64 + lane] = 0.f;
+                mat[lane] = 0.f;
             }
         }
         if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
+        if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
     }
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "slingbag.h"
 
 namespace sb {
@@ -195,13 +197,20 @@ __host__ __device__ inline uint32_t grid_coord(double x) {
 }
 
 // Ball-sensor distance: FP32 square root refined by one Newton step in FP64
-// (relative error ~1e-15, well below the FP64 decisions' needs).
-__device__ inline double dist64(double dx, double dy, double dz) {
+// (relative error ~1e-15, well below the FP64 decisions' needs).  `ri` receives
+// the FP32 reciprocal of the distance (relative error ~1e-7), which the
+// amplitude factors 1/r use.
+__device__ inline double dist64(double dx, double dy, double dz, float& ri) {
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const float rf = __builtin_amdgcn_sqrtf((float)r2);
+    ri = __builtin_amdgcn_rcpf(rf);
     const double r0 = (double)rf;
     const float e = (float)fma(-r0, r0, r2);
-    return r0 + (double)(e * (0.5f * __builtin_amdgcn_rcpf(rf)));
+    return r0 + (double)(e * (0.5f * ri));
+}
+__device__ inline double dist64(double dx, double dy, double dz) {
+    float ri;
+    return dist64(dx, dy, dz, ri);
 }
 
 // Window of one (ball, sensor) pair.  tau = (r - c t0)/delta is the arrival
@@ -214,6 +223,7 @@ __device__ inline double dist64(double dx, double dy, double dz) {
 template <int KERNEL>
 struct PairWin {
     double r;        // ball-sensor distance
+    float ri;        // 1 / r in FP32
     double a0;       // x_0
     int klo, W, m_hi;
     bool ok;         // sensor outside the uniform ball (r > 0 for the Gaussian ball)
@@ -224,7 +234,7 @@ template <int KERNEL>
 __device__ inline PairWin<KERNEL> pair_window(const OpParams& p, double rho, double dx, double dy,
                                               double dz) {
     PairWin<KERNEL> w;
-    w.r = dist64(dx, dy, dz);
+    w.r = dist64(dx, dy, dz, w.ri);
     const double h = (KERNEL == SB_KERNEL_UNIFORM) ? rho : (double)kGaussCut * rho;
     w.ok = (KERNEL == SB_KERNEL_UNIFORM) ? (w.r > rho * (double)p.delta) : (w.r > 0.0);
     const double tau = fma(w.r, p.inv_delta, -p.t0fs);
@@ -249,6 +259,40 @@ __device__ inline float wave_max(float v) {
 __device__ inline int wave_max_i(int v) {
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
     return v;
+}
+
+// Wave-wide reductions over DPP lane moves (no LDS round trip); every lane of
+// the wave must be active.  Quad and row mirrors reduce each row of 16 lanes,
+// then the four row results are read as scalars.
+template <int CTRL>
+__device__ inline int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <typename T, typename Op>
+__device__ inline T wave_reduce_dpp(T v, Op op) {
+    static_assert(sizeof(T) == 4, "32-bit values");
+    auto mv = [](T x, auto ctrl) {
+        const int r = dpp_move<decltype(ctrl)::value>(__builtin_bit_cast(int, x));
+        return __builtin_bit_cast(T, r);
+    };
+    v = op(v, mv(v, std::integral_constant<int, 0xB1>{}));    // quad_perm [1,0,3,2]
+    v = op(v, mv(v, std::integral_constant<int, 0x4E>{}));    // quad_perm [2,3,0,1]
+    v = op(v, mv(v, std::integral_constant<int, 0x141>{}));   // row_half_mirror
+    v = op(v, mv(v, std::integral_constant<int, 0x140>{}));   // row_mirror
+    const T r0 = __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const T r1 = __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const T r2 = __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const T r3 = __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return op(op(r0, r1), op(r2, r3));
+}
+__device__ inline float wave_min_all(float v) {
+    return wave_reduce_dpp(v, [](float a, float b) { return fminf(a, b); });
+}
+__device__ inline float wave_max_all(float v) {
+    return wave_reduce_dpp(v, [](float a, float b) { return fmaxf(a, b); });
+}
+__device__ inline int wave_max_all(int v) {
+    return wave_reduce_dpp(v, [](int a, int b) { return max(a, b); });
 }
 
 // Compiler-level ordering point for LDS traffic between lanes of one wave (the

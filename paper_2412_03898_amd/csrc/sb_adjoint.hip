@@ -286,6 +286,281 @@ __global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Uniform sphere, prefix-sum form.  Writing x_m = x_0 - m and summing by parts
+// once more (x_m - x_{m+1} = 1), with M = m_hi and r_m the residual at sample
+// k_lo + m:
+//   S_t = x_M r_M - x_1 r_0 + T0,   S_w(inside) = x_M^2 r_M - x_1^2 r_0 + (2 x_0 - 1) T0 - 2 T1,
+//   T0 = sum_{m=1}^{M-1} r_m,       T1 = sum_{m=1}^{M-1} m r_m,
+// (all zero when M = 0).  With exclusive prefix sums P0[k] = sum_{i<k} row_i and
+// P1[k] = sum_{i<k} i row_i of a staged residual row, T0 and T1 cost two LDS
+// reads per pair whatever the window length.
+//
+// Work item as above, but lane = ball in chunk order (no ranking: the cost no
+// longer depends on the window length) and the row is shared by the block: the
+// row origin of each sensor comes from the bounding box of the whole chunk.
+// Sensors are taken four at a time: wave w stages sensor 4g + w (its residual
+// row and the FP64 prefix sums, by a DPP scan over the wave), one barrier, then
+// every wave evaluates its balls against the four staged sensors.  The slots are
+// double-buffered, so one barrier per four sensors suffices.
+constexpr int kPfxRow = 128;      // staged residual samples per sensor
+
+struct PfxSlot {
+    double2 pfx[kPfxRow + 1];     // (P0[k], P1[k]), k = 0..kPfxRow
+    float rowf[kPfxRow];
+};
+
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active): row
+// shifts by 1, 2, 4, 8 within each row of 16 lanes, then the row totals are
+// broadcast to the rows above (DPP row_bcast:15 and row_bcast:31).
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_add_step(double v) {
+    const uint64_t bits = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)bits, CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(bits >> 32), CTRL, ROW_MASK, 0xF, true);
+    return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ inline double wave_incl_scan(double v) {
+    v = dpp_add_step<0x111, 0xF>(v);   // row_shr:1
+    v = dpp_add_step<0x112, 0xF>(v);   // row_shr:2
+    v = dpp_add_step<0x114, 0xF>(v);   // row_shr:4
+    v = dpp_add_step<0x118, 0xF>(v);   // row_shr:8
+    v = dpp_add_step<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add_step<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Stage one sensor's residual row: lane l holds samples o + 2l and o + 2l + 1.
+__device__ inline void stage_prefix(PfxSlot& sl, float e0, float e1, int lane) {
+    const int i0 = 2 * lane;
+    *reinterpret_cast<float2*>(&sl.rowf[i0]) = make_float2(e0, e1);
+    const double s0 = (double)e0 + (double)e1;
+    const double s1 = (double)i0 * (double)e0 + (double)(i0 + 1) * (double)e1;
+    const double I0 = wave_incl_scan(s0), I1 = wave_incl_scan(s1);
+    const double E0 = I0 - s0, E1 = I1 - s1;
+    sl.pfx[i0 + 1] = make_double2(E0 + (double)e0, E1 + (double)i0 * (double)e0);
+    sl.pfx[i0 + 2] = make_double2(I0, I1);
+    if (lane == 0) sl.pfx[0] = make_double2(0.0, 0.0);
+}
+
+template <int MREG, int OCC>
+__global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
+    static_assert(kPfxRow == 128, "two samples per lane");
+    __shared__ PfxSlot slots[2][4];
+    __shared__ float s_sx[kAdjMaxSplit], s_sy[kAdjMaxSplit], s_sz[kAdjMaxSplit];
+    __shared__ int s_org[kAdjMaxSplit];
+    __shared__ double s_fb[2 * SB_MAX_FOURIER];
+    __shared__ float s_red[4][8];
+
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const float delta = p.delta;
+    const float inv_delta_f = (float)p.inv_delta;
+    bool geometry = false, nonfinite = false;
+
+    for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
+        const ItemA it = decode_item_adj(p, item);
+        const Scene& sc = p.scenes[it.scene];
+        const int nb = min(kAdjChunk, sc.n_balls - it.chunk * kAdjChunk);
+        const int64_t first = sc.ball0 + (int64_t)it.chunk * kAdjChunk;
+        const int s_begin = it.split * p.s_per_split;
+        const int ns = min(p.S - s_begin, p.s_per_split);     // sensors of this split (<= kAdjMaxSplit)
+        const bool valid = tid < nb;
+        const int64_t b = first + (valid ? tid : 0);
+
+        __syncthreads();                 // the previous item is done with the sensor arrays
+        for (int j = tid; j < ns; j += 256) {
+            s_sx[j] = p.sensors[s_begin + j];
+            s_sy[j] = p.sensors[p.S + s_begin + j];
+            s_sz[j] = p.sensors[2 * p.S + s_begin + j];
+        }
+
+        float gb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float gd[5][MREG > 0 ? MREG : 1];
+        for (int a = 0; a < 5; ++a)
+            for (int m = 0; m < (MREG > 0 ? MREG : 1); ++m) gd[a][m] = 0.f;
+
+        for (int f = 0; f < sc.n_frames; ++f) {
+            const int gf = sc.frame0 + f;
+            const float t = p.frame_t[gf];
+            __syncthreads();             // the previous frame is done with s_fb, s_org, slots
+            if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
+            __syncthreads();
+            BallF bl;
+            bool live = false;
+            if (valid) {
+                live = deform_ball(p, b, t, s_fb, bl);
+                nonfinite |= !live;
+            }
+            // bounding box (rounded outwards) and largest size of the chunk's live balls
+            float red[7];
+            red[0] = live ? __double2float_rd(bl.x) : 3.0e38f;
+            red[1] = live ? __double2float_rd(bl.y) : 3.0e38f;
+            red[2] = live ? __double2float_rd(bl.z) : 3.0e38f;
+            red[3] = live ? __double2float_ru(bl.x) : -3.0e38f;
+            red[4] = live ? __double2float_ru(bl.y) : -3.0e38f;
+            red[5] = live ? __double2float_ru(bl.z) : -3.0e38f;
+            red[6] = live ? bl.rhof : 0.f;
+            for (int a = 0; a < 3; ++a) red[a] = wave_min_all(red[a]);
+            for (int a = 3; a < 7; ++a) red[a] = wave_max_all(red[a]);
+            if (lane == 0)
+                for (int a = 0; a < 7; ++a) s_red[wid][a] = red[a];
+            __syncthreads();
+            float lo[3], hi[3], rmax = 0.f;
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(fminf(s_red[0][a], s_red[1][a]), fminf(s_red[2][a], s_red[3][a]));
+                hi[a] = fmaxf(fmaxf(s_red[0][3 + a], s_red[1][3 + a]), fmaxf(s_red[2][3 + a], s_red[3][3 + a]));
+            }
+            rmax = fmaxf(fmaxf(s_red[0][6], s_red[1][6]), fmaxf(s_red[2][6], s_red[3][6]));
+            if (!(lo[0] <= hi[0])) continue;           // no live ball in the chunk (same in every thread)
+            const double hmax = (double)rmax;
+            // row origins: every window of the chunk starts at or after o + 1
+            for (int j = tid; j < ns; j += 256) {
+                double dmin, dmax;
+                box_distance_range(lo, hi, (double)s_sx[j], (double)s_sy[j], (double)s_sz[j], dmin, dmax);
+                const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
+                s_org[j] = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
+            }
+            __syncthreads();
+
+            // per-ball constants of this frame
+            const float rho = live ? bl.rhof : 0.f;
+            const double rhod = live ? bl.rho : 0.0;
+            const double h_half = rhod - 0.5;
+            const double r_in = rhod * (double)delta;          // sensor must be farther than this
+            const bool w_ok = live && rhod < 1.0e6;
+            const int W = w_ok ? (int)(2.0 * rhod) + 2 : 0;
+            const float* res_frame = p.residual + (int64_t)gf * p.S * p.T;
+            float g5[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+
+            auto load_pair = [&](int j, float& e0, float& e1) {
+                const int k = s_org[j] + 2 * lane;
+                const float* rr = res_frame + (int64_t)(s_begin + j) * p.T;
+                e0 = (k >= 0 && k < p.T) ? rr[k] : 0.f;
+                e1 = (k + 1 >= 0 && k + 1 < p.T) ? rr[k + 1] : 0.f;
+            };
+            float e0 = 0.f, e1 = 0.f;
+            if (wid < ns) load_pair(wid, e0, e1);
+            const int ngroups = (ns + 3) >> 2;
+            for (int g = 0; g < ngroups; ++g) {
+                const int buf = g & 1;
+                if (4 * g + wid < ns) stage_prefix(slots[buf][wid], e0, e1, lane);
+                if (4 * g + 4 + wid < ns) load_pair(4 * g + 4 + wid, e0, e1);
+                __syncthreads();
+                const int nu = min(4, ns - 4 * g);
+                for (int u = 0; u < nu; ++u) {
+                    const int j = 4 * g + u;
+                    const PfxSlot& sl = slots[buf][u];
+                    const double dx = bl.x - (double)s_sx[j];
+                    const double dy = bl.y - (double)s_sy[j];
+                    const double dz = bl.z - (double)s_sz[j];
+                    float inv_r;
+                    const double r = dist64(dx, dy, dz, inv_r);
+                    const double tau = fma(r, p.inv_delta, -p.t0fs);
+                    const double kl = floor(tau - h_half);
+                    const double a0d = tau - kl + 0.5;
+                    const bool geo = w_ok && r > r_in;
+                    geometry |= w_ok && !geo;
+                    const bool use = geo && fabs(kl) < 5.0e8;
+                    const int klo = use ? (int)kl : 0;
+                    const int tl = klo - s_org[j];
+                    const bool in_row = use && tl >= 0 && tl + W <= kPfxRow;
+                    // inside boundaries m = 1..M (M decided in FP64)
+                    const int M = use ? (int)ceil(a0d + rhod) - 1 : 0;
+                    // prefix form (lanes outside the row read row entry 0 and discard it)
+                    const int t0 = in_row ? tl : 0, iM = in_row ? tl + M : 0;
+                    const float r0 = sl.rowf[t0], rM = sl.rowf[iM];
+                    const double2 pa = sl.pfx[t0 + 1], pb = sl.pfx[iM];
+                    const double T0 = pb.x - pa.x;
+                    const double T1 = (pb.y - pa.y) - (double)t0 * T0;
+                    const double xM = a0d - (double)M, x1 = a0d - 1.0;
+                    double St = fma(xM, (double)rM, fma(-x1, (double)r0, T0));
+                    double Sw = fma(xM * xM, (double)rM, fma(-x1 * x1, (double)r0, fma(2.0 * a0d - 1.0, T0, -2.0 * T1)));
+                    float Sr = rM - r0;
+                    const bool any = M >= 1;
+                    if (!(in_row && any)) { St = 0.0; Sw = 0.0; Sr = 0.f; }
+                    // windows outside the staged row: boundaries straight from global memory
+                    const bool glob = use && !in_row;
+                    if (__ballot(glob)) {
+                        if (glob) {
+                            const float* rres = res_frame + (int64_t)(s_begin + j) * p.T;
+                            const float q0 = (klo >= 0 && klo < p.T) ? rres[klo] : 0.f;
+                            float rp = q0, sw = 0.f, st = 0.f, x = (float)a0d;
+                            for (int m = 1; m <= M; ++m) {
+                                x -= 1.f;
+                                const int k = klo + m;
+                                const float rm = (k >= 0 && k < p.T) ? rres[k] : 0.f;
+                                const float dr = rm - rp;
+                                rp = rm;
+                                sw = fmaf(x * x, dr, sw);
+                                st = fmaf(x, dr, st);
+                            }
+                            St = st;
+                            Sw = sw;
+                            Sr = rp - q0;
+                        }
+                    }
+                    if (use) {
+                        const float A = fmaf(-rho * rho, Sr, (float)Sw);
+                        const float Bs = (float)St;
+                        const float Cr = delta * 0.25f * inv_r;   // C / P_f
+                        const float C = bl.amp * Cr;
+                        const float dLdr = 2.f * C * Bs * inv_delta_f - C * A * inv_r;
+                        const float dLdR = -2.f * rho * C * Sr * inv_delta_f;
+                        const float dLdP = Cr * A;
+                        g5[0] = fmaf(dLdr, (float)dx * inv_r, g5[0]);
+                        g5[1] = fmaf(dLdr, (float)dy * inv_r, g5[1]);
+                        g5[2] = fmaf(dLdr, (float)dz * inv_r, g5[2]);
+                        g5[3] += dLdR;
+                        g5[4] += dLdP;
+                    }
+                }
+            }
+            // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame
+            if (live) {
+                float base[5];
+                for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
+                for (int a = 0; a < 5; ++a) {
+                    const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
+                    const float hh = (float)eval_H(p, b, a, t, s_fb);
+                    gb[a] += additive ? g5[a] : g5[a] * (1.f + hh);
+                    const float gs = additive ? g5[a] : g5[a] * base[a];
+                    if (MREG > 0) {
+                        for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)s_fb[m], gd[a][m]);
+                    } else if (p.basis != SB_BASIS_STATIC) {
+                        for (int m = 0; m < p.M; ++m)
+                            unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b,
+                                            gs * eval_dH(p, b, a, m, t, s_fb));
+                    }
+                }
+            }
+        }
+        if (valid) {
+            for (int a = 0; a < 5; ++a) {
+                unsafeAtomicAdd(p.grad_balls + (int64_t)a * p.B + b, gb[a]);
+                if (MREG > 0)
+                    for (int m = 0; m < MREG; ++m)
+                        unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b, gd[a][m]);
+            }
+        }
+    }
+    if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
+    if (nonfinite) raise_flag(p.flags, SB_FLAG_NONFINITE);
+}
+
+template <int MREG, int OCC>
+static hipError_t launch_adj_u(const OpParams& p, hipStream_t st) {
+    int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((adjoint_uniform_kernel<MREG, OCC>), dim3((unsigned)grid), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+template <int OCC>
+static hipError_t launch_adj_um(const OpParams& p, hipStream_t st) {
+    const bool reg = p.basis == SB_BASIS_FOURIER && p.M == 4;
+    return reg ? launch_adj_u<4, OCC>(p, st) : launch_adj_u<0, OCC>(p, st);
+}
+
 template <int UROW, int KERNEL, int MREG, int OCC>
 static hipError_t launch_adj_t(const OpParams& p, hipStream_t st) {
     int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
@@ -303,10 +578,10 @@ static hipError_t launch_adj_m(const OpParams& p, hipStream_t st) {
 
 // tc.ucap: residual row length; tc.nw: blocks per CU requested from the compiler (occupancy)
 hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
-    if (kernel == SB_KERNEL_UNIFORM && tc.ucap == 128) {
-        if (tc.nw == 2) return launch_adj_m<128, 0, 2>(p, st);
-        if (tc.nw == 3) return launch_adj_m<128, 0, 3>(p, st);
-        if (tc.nw == 4) return launch_adj_m<128, 0, 4>(p, st);
+    if (kernel == SB_KERNEL_UNIFORM && tc.ucap == kPfxRow) {
+        if (tc.nw == 2) return launch_adj_um<2>(p, st);
+        if (tc.nw == 3) return launch_adj_um<3>(p, st);
+        if (tc.nw == 4) return launch_adj_um<4>(p, st);
     }
     if (kernel == SB_KERNEL_GAUSS && tc.ucap == 192 && tc.nw == 2) return launch_adj_m<192, 1, 2>(p, st);
     return hipErrorInvalidValue;

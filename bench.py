@@ -12,7 +12,7 @@ Fibonacci hemisphere, 4,096 samples at 40 MHz.
 
 Prints ONE JSON line.  `value` is ball*sensor*frame pairs per second through
 forward + adjoint (GPairs/s).  The roofline object reports the dominant kernel
-against the chip's vector-ALU peak (the path has no dense contraction and its
+in vector-ALU lane operations against the chip's lane-operation peak (the path has no dense contraction and its
 DRAM traffic is small next to its arithmetic); the cpu_baseline object times
 the FP64 CPU oracle on the host cores over the same workload.
 """
@@ -28,9 +28,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Vector-ALU peak without packed FP32 (packed FP32 is not generated in this
-# build): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP per FMA x 2.4 GHz.
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.64
+# Vector-ALU peak in lane operations (an FMA counts once; packed FP32 is not
+# generated in this build): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # 39.32 T lane-ops/s
 
 # Learning rates of Sec. 3.2 (coordinates, peak pressure, size, deformation).
 LR_POS, LR_P, LR_R, LR_DEF = 5e-7, 5e-4, 5e-7, 5e-6
@@ -45,13 +45,15 @@ def workloads():
     }
 
 
-def flop_model(wl):
-    """Algorithmic FLOPs of one forward and one adjoint launch (FMA = 2).
+def op_model(wl):
+    """Algorithmic vector-ALU lane operations of one forward and one adjoint launch.
 
     Per (ball, sensor, frame) pair with a window of W samples (W = floor(2 R_f/delta) + 2
-    for the uniform sphere): geometry 16 FLOP; forward 7 FLOP per sample; adjoint
-    13 FLOP per window boundary (W + 1 of them) plus 20 to form the five
-    per-pair derivatives.
+    for the uniform sphere), counting the direct evaluation of the method: 40 for the
+    FP64 pair geometry in each kernel, 8 per sample in the forward (clamp, square,
+    difference, scale, accumulate) and 14 per sample in the adjoint (residual difference
+    and the three weighted sums).  The kernels evaluate the interior of each window in
+    closed form and execute fewer operations than this count.
     """
     import numpy as np
     delta = wl.c / wl.fs
@@ -72,8 +74,8 @@ def flop_model(wl):
             W = np.floor(2.0 * Rf / delta) + 2.0
             sumW += float(W.sum()) * S
             pairs += len(R) * S
-    fwd = 16.0 * pairs + 7.0 * sumW
-    adj = 16.0 * pairs + 13.0 * (sumW + pairs) + 20.0 * pairs
+    fwd = 40.0 * pairs + 8.0 * sumW
+    adj = 40.0 * pairs + 14.0 * sumW
     return {"forward": fwd, "adjoint": adj, "pairs": pairs, "mean_window": sumW / max(pairs, 1)}
 
 
@@ -315,7 +317,7 @@ def main():
     pairs = pb.pairs()
     ms_step = elapsed / args.steps * 1e3
     value = pairs * args.steps / elapsed / 1e9
-    fm = flop_model(wl)
+    fm = op_model(wl)
     per_kernel = {k: (ms / n if n else None) for k, (ms, n) in kt.items()}
     dom = max(("forward", "adjoint"), key=lambda k: per_kernel[k] or 0.0)
     achieved = fm[dom] / (per_kernel[dom] * 1e-3) / 1e12
@@ -339,9 +341,9 @@ def main():
                    "tuning": {"forward_column": choice[0], "adjoint_occupancy": choice[1],
                               "adjoint_items": choice[2]}},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-                     "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
-                     "flop_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3)},
+                     "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                     "ops_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3)},
         "kernel_ms": {k: (round(v, 4) if v is not None else None) for k, v in per_kernel.items()},
         "graph_ms_per_step": None if ms_graph is None else round(ms_graph, 4),
         "device_flags": flags,

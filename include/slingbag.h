@@ -203,9 +203,12 @@ int slingbag_plan_destroy(sb_plan* plan);
  * change speed only; results differ at most by the order of FP32 atomic
  * additions.  The autotuner (python: paper_2412_03898_amd.tune) times the
  * candidates on the caller's own shapes and sets the fastest.
- *   SB_TUNE_FWD_COLUMN     forward LDS column length: 64 or 128 samples (uniform sphere)
- *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4
- *   SB_TUNE_ADJ_ITEMS      adjoint work items the sensor split aims for: 1 .. 2^22
+ *   SB_TUNE_FWD_COLUMN     forward LDS column length: 64 or 128 samples (uniform sphere);
+ *                          default 64
+ *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4;
+ *                          default 4
+ *   SB_TUNE_ADJ_ITEMS      adjoint work items the sensor split aims for: 1 .. 2^22;
+ *                          default 8192
  * Unknown keys or values return SB_ERR_INVALID_ARG and change nothing. */
 #define SB_TUNE_FWD_COLUMN     1
 #define SB_TUNE_ADJ_OCCUPANCY  2

@@ -482,21 +482,30 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                     const bool glob = use && !in_row;
                     if (__ballot(glob)) {
                         if (glob) {
+                            // the same closed form, summing r_1..r_{M-1} straight from the
+                            // residual row in global memory, eight loads in flight at a time
                             const float* rres = res_frame + (int64_t)(s_begin + j) * p.T;
-                            const float q0 = (klo >= 0 && klo < p.T) ? rres[klo] : 0.f;
-                            float rp = q0, sw = 0.f, st = 0.f, x = (float)a0d;
-                            for (int m = 1; m <= M; ++m) {
-                                x -= 1.f;
+                            auto at = [&](int m) {
                                 const int k = klo + m;
-                                const float rm = (k >= 0 && k < p.T) ? rres[k] : 0.f;
-                                const float dr = rm - rp;
-                                rp = rm;
-                                sw = fmaf(x * x, dr, sw);
-                                st = fmaf(x, dr, st);
+                                return (k >= 0 && k < p.T) ? rres[k] : 0.f;
+                            };
+                            const float q0 = at(0), qM = at(M);
+                            double g0 = 0.0, g1 = 0.0;
+                            for (int m0 = 1; m0 < M; m0 += 8) {
+                                float v[8];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) v[u] = (m0 + u < M) ? at(m0 + u) : 0.f;
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    g0 += (double)v[u];
+                                    g1 = fma((double)(m0 + u), (double)v[u], g1);
+                                }
                             }
-                            St = st;
-                            Sw = sw;
-                            Sr = rp - q0;
+                            const double xMg = a0d - (double)M, x1g = a0d - 1.0;
+                            St = fma(xMg, (double)qM, fma(-x1g, (double)q0, g0));
+                            Sw = fma(xMg * xMg, (double)qM, fma(-x1g * x1g, (double)q0, fma(2.0 * a0d - 1.0, g0, -2.0 * g1)));
+                            Sr = qM - q0;
+                            if (M < 1) { St = 0.0; Sw = 0.0; Sr = 0.f; }
                         }
                     }
                     if (use) {

@@ -118,9 +118,9 @@ static int validate_batch(const sb_batch* batch, Shape& sh) {
 // and adjoint item count.  They change speed, not results (beyond the order of
 // floating-point atomics).
 struct Tuning {
-    int fwd_ucap = 128;        // 64 or 128 samples per LDS column
-    int adj_occ = 2;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
-    int adj_items = 4096;      // adjoint items the sensor split aims for
+    int fwd_ucap = 64;         // 64 or 128 samples per LDS column
+    int adj_occ = 4;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
+    int adj_items = 8192;      // adjoint items the sensor split aims for
 };
 static Tuning g_tune;
 

@@ -2,20 +2,20 @@
 //
 // Work item = (scene, frame, chunk of G consecutive balls, block of 64*NW
 // sensors).  The block stages the chunk's deformed balls (Eq. 1, recomputed
-// here) in LDS and splits the chunk into sub-groups: runs of consecutive balls
-// that share a cell of the canonical grid at a level chosen so that a
-// sub-group's arrival-time spread fits the LDS tile.  With balls in Morton order
-// every such cell is one run.
-//
-// Each wave owns 64 sensors, one per lane, and each lane owns one column of the
-// wave's LDS trace tile T[UCAP][64] (column c lives in bank c mod 32: no
-// conflicts while lanes add their windows at different samples).  Per
-// sub-group, each lane places its column at the arrival sample of the
-// sub-group's bounding box, adds the windows of the sub-group's balls, and the
-// wave then flushes the tile: each 64-sample block is transposed in place (swap
-// pairs along diagonals, conflict-free) so that one row holds 64 consecutive
-// samples of one sensor, and is added to the global trace with one coalesced
-// FP32 atomic per row.  A window that does not fit the tile is added to global
+// here) in LDS.  Each wave owns 64 sensors, one per lane, and each lane owns
+// one column of the wave's LDS trace tile T[UCAP][64] (column c lives in bank
+// c mod 32: no conflicts while lanes add their windows at different samples).
+// The column of a lane covers UCAP consecutive samples of its sensor from an
+// origin o.  The wave walks the chunk's balls in order; the windows land in
+// the columns as long as they fit, and when a window would leave its column
+// in some lane the wave flushes the tile to the global trace and re-centres
+// every lane's column on that ball's window.  With balls in a spatially
+// coherent order (slingbag_order) consecutive balls arrive at nearly the same
+// sample at every sensor, so one flush covers on the order of a hundred balls,
+// also when every ball is displaced differently at each frame.  The flush
+// transposes each touched 64-sample block through LDS so that one row holds 64
+// consecutive samples of one sensor, and adds it to the global trace with one
+// coalesced FP32 atomic per row.  Windows longer than the tile go to global
 // memory directly.
 //
 // Trace of one ball in sample units (tau = (r - c t0)/delta, rho = R_f/delta):
@@ -109,13 +109,11 @@ __device__ inline void add_window(float* c, int W, float x0, float rho, float C)
 
 // Per-pair quantities of one ball for the wave's 64 sensors (one per lane).
 struct FwdPair {
-    float C, x0;     // amplitude and boundary 0 (zero in lanes that add nothing to the tile)
-    float Cg, xg;    // the same for the direct path to global memory
+    float Cg, xg;    // amplitude and boundary 0
     float rhof;
-    int tl;          // tile row of sample 0 (0 in lanes that add nothing to the tile)
     int klo;         // sample index of sample 0
     int W;           // window length (the same in every lane)
-    bool in_tile, glob;
+    bool in_tile;    // this lane has a window to add
 };
 
 template <int KERNEL>
@@ -150,18 +148,15 @@ __device__ inline bool add_window_global(float* row, int klo, int T, int W, floa
 template <int NW, int G, int UCAP, int KERNEL>
 __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
     static_assert(UCAP % 64 == 0, "tile length must be a multiple of 64");
+    static_assert(G == 64 * NW, "one ball per thread when staging");
     __shared__ BallF sball[G];
-    __shared__ uint32_t scell[G][3];     // canonical grid coordinates of the base positions
-    __shared__ int sub_start[G + 1];     // sub-group boundaries within the chunk
-    __shared__ int wave_cnt[NW];
-    __shared__ float sred[NW][2];
-    __shared__ int s_nsub, s_level;
     __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
     __shared__ float tile[NW][(UCAP + 1) * 64];     // per wave: a pad row, then UCAP rows of 64 sensors
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     float* const tw = &tile[wid][64];
     for (int k = -1; k < UCAP; ++k) tw[k * 64 + lane] = 0.f;
+    bool clipped = false, geometry = false, nonfinite = false;
 
     for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
         const Item it = decode_item(p, item);
@@ -170,102 +165,28 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         const float t = p.frame_t[gf];
         const int64_t first = sc.ball0 + (int64_t)it.group * G;
         const int nb = min(G, sc.n_balls - it.group * G);
-        __syncthreads();   // the previous item is done with sball/scell/sub_start
+        __syncthreads();   // the previous item is done with sball and s_fb
 
-        // ---- stage the chunk: deformed balls, grid cells, size and displacement bounds
+        // ---- stage the chunk's deformed balls (Eq. 1, one per thread)
         if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
         __syncthreads();
-        const double* fb = s_fb;
-        float rho_max = 0.f, disp_max = 0.f;
-        for (int i = tid; i < G; i += 64 * NW) {
+        {
             BallF bl;
-            uint32_t c3[3] = {0u, 0u, 0u};
-            if (i < nb) {
-                const int64_t b = first + i;
-                if (!deform_ball(p, b, t, fb, bl)) raise_flag(p.flags, SB_FLAG_NONFINITE);
+            if (tid < nb) {
+                nonfinite |= !deform_ball(p, first + tid, t, s_fb, bl);
                 // amplitude scale of the trace: P_f delta / 4 (uniform), P_f rho^2 delta / 2 (Gaussian)
                 bl.amp = (KERNEL == SB_KERNEL_UNIFORM)
                              ? (float)((double)bl.amp * (double)p.delta * 0.25)
                              : (float)((double)bl.amp * bl.rho * bl.rho * (double)p.delta * 0.5);
-                const double bx = p.balls[b], by = p.balls[p.B + b], bz = p.balls[2 * p.B + b];
-                c3[0] = grid_coord(bx);
-                c3[1] = grid_coord(by);
-                c3[2] = grid_coord(bz);
-                if (bl.rho >= 0.0) {
-                    rho_max = fmaxf(rho_max, bl.rhof);
-                    const double dd = fmax(fabs(bl.x - bx), fmax(fabs(bl.y - by), fabs(bl.z - bz)));
-                    disp_max = fmaxf(disp_max, (float)dd);
-                }
             } else {
                 bl.x = bl.y = bl.z = 0.0;
                 bl.rho = -1.0;
                 bl.rhof = -1.f;
                 bl.amp = 0.f;
             }
-            sball[i] = bl;
-            scell[i][0] = c3[0];
-            scell[i][1] = c3[1];
-            scell[i][2] = c3[2];
-        }
-        rho_max = wave_max_all(rho_max);   // every lane takes exactly one ball slot above
-        disp_max = wave_max_all(disp_max);
-        if (lane == 0) { sred[wid][0] = rho_max; sred[wid][1] = disp_max; }
-        __syncthreads();
-        if (tid == 0) {
-            float rm = 0.f, dm = 0.f;
-            for (int w = 0; w < NW; ++w) { rm = fmaxf(rm, sred[w][0]); dm = fmaxf(dm, sred[w][1]); }
-            // largest grid level whose cell keeps the arrival spread inside the tile:
-            // a sub-group's deformed bounding box has a diagonal of at most
-            // sqrt(3) (side + 2 dm) (dm: largest per-axis displacement), and a
-            // column must hold that spread plus one window (2h + 2) and the
-            // origin margins (4 samples), with 2 samples to spare.
-            const double h = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rm : (double)kGaussCut * rm;
-            const double room = ((double)(UCAP - 8) - 2.0 * h) * (double)p.delta -
-                                2.0 * 1.7320508075688772 * (double)dm;
-            int level = 0;
-            while (level < kGridBits - 1 && 1.7320508075688772 * kGridQuantum * (double)(1 << (level + 1)) <= room)
-                ++level;
-            s_level = level;
+            sball[tid] = bl;
         }
         __syncthreads();
-        // ---- sub-groups: runs of equal cell at the chosen level (block-wide compaction).
-        // A ball whose cell differs from both neighbours while they agree (a ball
-        // that drifted just across a cell face since the balls were ordered) stays
-        // in the surrounding run; the run's bounding box, not its cell, sizes the
-        // columns, so this only keeps runs long.
-        {
-            const int level = s_level;
-            const int i = tid;                 // G == 64 * NW (one ball per thread)
-            auto same = [&](int u, int v) {
-                return ((scell[u][0] >> level) == (scell[v][0] >> level)) &&
-                       ((scell[u][1] >> level) == (scell[v][1] >> level)) &&
-                       ((scell[u][2] >> level) == (scell[v][2] >> level));
-            };
-            bool flag = false;
-            if (i < nb) {
-                flag = (i == 0) || !same(i, i - 1);
-                if (flag && i > 0) {
-                    const bool intruder = i + 1 < nb && same(i - 1, i + 1);
-                    const bool after_intruder = i >= 2 && !same(i - 1, i - 2) && same(i - 2, i);
-                    if (intruder || after_intruder) flag = false;
-                }
-            }
-            const unsigned long long m = __ballot(flag);
-            const int before = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) wave_cnt[wid] = __popcll(m);
-            __syncthreads();
-            int base = 0;
-            for (int w = 0; w < wid; ++w) base += wave_cnt[w];
-            if (flag) sub_start[base + before] = i;
-            if (tid == 0) {
-                int tot = 0;
-                for (int w = 0; w < NW; ++w) tot += wave_cnt[w];
-                s_nsub = tot;
-                sub_start[tot] = nb;
-            }
-            __syncthreads();
-        }
-        const int nsub = s_nsub;
 
         const int s = it.sblock * 64 * NW + wid * 64 + lane;
         const bool active = s < p.S;
@@ -273,84 +194,22 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
         const int64_t row_off = ((int64_t)gf * p.S + (active ? s : 0)) * p.T;   // this lane's trace row
         float* out_row = p.signals + row_off;
-        bool clipped = false, geometry = false;
 
-        for (int sg = 0; sg < nsub; ++sg) {
-            const int i0 = sub_start[sg], i1 = sub_start[sg + 1];
-            // bounding box (rounded outwards) and largest size of the sub-group
-            float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
-            float rmax = 0.f;
-            for (int i = i0 + lane; i < i1; i += 64) {
-                const BallF& bl = sball[i];
-                if (bl.rho < 0.0) continue;
-                lo[0] = fminf(lo[0], __double2float_rd(bl.x)); hi[0] = fmaxf(hi[0], __double2float_ru(bl.x));
-                lo[1] = fminf(lo[1], __double2float_rd(bl.y)); hi[1] = fmaxf(hi[1], __double2float_ru(bl.y));
-                lo[2] = fminf(lo[2], __double2float_rd(bl.z)); hi[2] = fmaxf(hi[2], __double2float_ru(bl.z));
-                rmax = fmaxf(rmax, bl.rhof);
-            }
-            for (int a = 0; a < 3; ++a) { lo[a] = wave_min_all(lo[a]); hi[a] = wave_max_all(hi[a]); }
-            rmax = wave_max_all(rmax);
-            if (!(lo[0] <= hi[0])) continue;          // no valid ball in this sub-group
-            const double hmax = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rmax : (double)kGaussCut * rmax;
-            double dmin, dmax;
-            box_distance_range(lo, hi, sx, sy, sz, dmin, dmax);
-            // column origin: every window of the sub-group starts at or after o + 1
-            const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
-            const int o = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
-            int kmax = -1;
+        // Each lane's column covers samples o .. o + UCAP - 1 of its sensor.  The
+        // balls are taken in chunk order (spatially coherent after slingbag_order);
+        // when a window does not fit its column in some lane, the wave flushes the
+        // tile and re-centres every lane's column on that ball's window.
+        int o = -(1 << 30);          // no column yet: the first window triggers the set-up
+        int kmax = -1;               // last tile row written (wave-wide max at the flush)
 
-            // pair set-up of ball i for this wave's sensors; windows that do not fit
-            // the tile, invalid balls and inactive lanes add zeros at rows 0..2
-            auto prep = [&](int i) {
-                FwdPair f;
-                const BallF bl = sball[i];
-                const bool valid = bl.rho >= 0.0;
-                const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
-                const bool too_long = valid && h >= 1.0e6;       // window longer than any record
-                const int Wb = (int)(2.0 * fmin(fmax(h, 0.0), 1.0e6)) + 2;
-                f.W = __builtin_amdgcn_readfirstlane(Wb);
-                const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, bl.x - sx, bl.y - sy, bl.z - sz);
-                const bool use = active && valid && !too_long;
-                geometry |= use && !w.ok;
-                clipped |= (active && too_long) || (use && w.ok && !w.in_range);
-                const bool part = use && w.ok && w.in_range;
-                const int tl = w.klo - o;
-                const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
-                f.in_tile = part && tl >= 0 && tl + rows <= UCAP;
-                f.glob = part && !f.in_tile;
-                f.Cg = bl.amp * w.ri;                            // amp holds the amplitude scale (staging)
-                f.xg = (float)w.a0;
-                f.C = f.in_tile ? f.Cg : 0.f;
-                f.x0 = f.in_tile ? f.xg : 0.f;
-                f.tl = f.in_tile ? tl : 0;
-                f.klo = w.klo;
-                f.rhof = bl.rhof;
-                return f;
-            };
-            auto apply = [&](const FwdPair& f) {
-                const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
-                if (rows <= UCAP) add_window<KERNEL>(tw + f.tl * 64 + lane, f.W, f.x0, f.rhof, f.C);
-                if (f.in_tile) kmax = max(kmax, f.tl + f.W - 1);
-                if (__ballot(f.glob)) {
-                    if (f.glob) clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
-                }
-            };
-            // software pipeline: the set-up of ball i+1 overlaps the tile update of ball i
-            FwdPair cur = prep(i0);
-            for (int i = i0; i < i1; ++i) {
-                const FwdPair nxt = prep(min(i + 1, i1 - 1));
-                apply(cur);
-                cur = nxt;
-            }
-
-            // ---- flush, per touched 64-sample block q: each lane reads its column
-            // (64 samples of its sensor) into registers and writes it back as row
-            // `lane` of a 64 x 65 matrix that starts 64 floats before the block
-            // (in the previous, already flushed block, or the pad row before the
-            // tile); the row stride of 65 keeps both the row writes and the column
-            // reads of the matrix conflict-free.  Row a then holds 64 consecutive
-            // samples of sensor a, added to the global trace with one coalesced FP32
-            // atomic per row.
+        // ---- flush, per touched 64-sample block q: each lane reads its column
+        // (64 samples of its sensor) into registers and writes it back as row
+        // `lane` of a 64 x 65 matrix that starts 64 floats before the block (in
+        // the previous, already flushed block, or the pad row before the tile); the
+        // row stride of 65 keeps both the row writes and the column reads of the
+        // matrix conflict-free.  Row a then holds 64 consecutive samples of sensor
+        // a, added to the global trace with one coalesced FP32 atomic per row.
+        auto flush = [&]() {
             const int nblk = (wave_max_all(kmax) + 64) >> 6;
             for (int q = 0; q < nblk; ++q) {
                 float* const blk = tw + q * 64 * 64;
@@ -386,10 +245,59 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 for (int k = 0; k < 64; ++k) blk[k * 64 + lane] = 0.f;
                 mat[lane] = 0.f;
             }
+            kmax = -1;
+        };
+
+        // pair set-up of ball i for this wave's sensors
+        auto prep = [&](int i) {
+            FwdPair f;
+            const BallF bl = sball[i];
+            const bool valid = bl.rho >= 0.0;
+            const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
+            const bool too_long = valid && h >= 1.0e6;       // window longer than any record
+            const int Wb = (int)(2.0 * fmin(fmax(h, 0.0), 1.0e6)) + 2;
+            f.W = __builtin_amdgcn_readfirstlane(Wb);
+            const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, bl.x - sx, bl.y - sy, bl.z - sz);
+            const bool use = active && valid && !too_long;
+            geometry |= use && !w.ok;
+            clipped |= (active && too_long) || (use && w.ok && !w.in_range);
+            f.in_tile = use && w.ok && w.in_range;            // the window exists (placed at apply)
+            f.Cg = bl.amp * w.ri;                            // amp holds the amplitude scale (staging)
+            f.xg = (float)w.a0;
+            f.klo = w.klo;
+            f.rhof = bl.rhof;
+            return f;
+        };
+        auto apply = [&](const FwdPair& f) {
+            const bool part = f.in_tile;
+            const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
+            if (rows <= UCAP) {
+                int tl = f.klo - o;
+                if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
+                    flush();
+                    if (part) o = f.klo - ((UCAP - rows) >> 1);
+                    tl = f.klo - o;
+                }
+                // lanes without a window add zeros at rows 0..2
+                const int tr = part ? tl : 0;
+                add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
+                if (part) kmax = max(kmax, tl + f.W - 1);
+            } else if (part) {
+                clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
+            }
+        };
+        // software pipeline: the set-up of ball i+1 overlaps the tile update of ball i
+        FwdPair cur = prep(0);
+        for (int i = 0; i < nb; ++i) {
+            const FwdPair nxt = prep(min(i + 1, nb - 1));
+            apply(cur);
+            cur = nxt;
         }
-        if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
-        if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
+        flush();
     }
+    if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
+    if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
+    if (nonfinite) raise_flag(p.flags, SB_FLAG_NONFINITE);
 }
 
 template <int NW, int G, int UCAP, int KERNEL>

@@ -1,0 +1,300 @@
+"""Iterative reconstruction (IR) loop of the 4D point-cloud model (Sec. 2.2, Sec. 3.2).
+
+One iteration: forward of every ball at every frame, L2 loss against the
+measured signals, adjoint (gradient of every base attribute and deformation
+coefficient), and one Adam update per parameter group with the learning rates
+of Sec. 3.2 (coordinates 5e-7, peak pressure 5e-4, size 5e-7, deformation
+coefficients 5e-6, in SI units) and their step decay (x0.1 every 160
+iterations).  Forward, loss and adjoint run as one captured graph per
+iteration; the Adam updates are four launches of the library's fused kernel.
+
+State (parameters, Adam moments, iteration count, loss history) is saved to
+and restored from an .npz file (plain arrays, no pickled objects), so a run
+can stop and resume where it left off.
+
+`python -m paper_2412_03898_amd.ir` runs the large 4D scene (1,000,000 vessel
+balls, 32 frames, 2,048 sensors, 4,096 samples) for 200 iterations from a
+perturbed start and prints one JSON line with ms per iteration, the loss curve
+and the peak device memory, next to the frame-by-frame path (each frame an
+independent static scene) over a few iterations.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import ops
+
+# Sec. 3.2: initial learning rates and step decay
+LR_POS, LR_P, LR_R, LR_DEF = 5e-7, 5e-4, 5e-7, 5e-6
+DECAY_STEP, DECAY_RATE = 160, 0.1
+
+
+def step_decay(it: int, step_size: int = DECAY_STEP, rate: float = DECAY_RATE) -> float:
+    """Learning-rate factor at 0-based iteration `it` (x rate every step_size iterations)."""
+    return rate ** (it // step_size)
+
+
+class IRLoop:
+    """IR loop on device tensors.
+
+    pb: binding.Problem; balls [5][B] and deform [5][M][B] (or None) are updated in
+    place; measured [F][S][T] holds the measured signals.
+    """
+
+    def __init__(self, pb, balls, deform, frame_t, sensors, measured, use_graph: bool = True,
+                 lrs=(LR_POS, LR_R, LR_P, LR_DEF), decay_step: int = DECAY_STEP,
+                 decay_rate: float = DECAY_RATE):
+        self.pb, self.balls, self.deform = pb, balls, deform
+        self.frame_t, self.sensors, self.measured = frame_t, sensors, measured
+        self.lrs = tuple(float(x) for x in lrs)
+        self.decay_step, self.decay_rate = int(decay_step), float(decay_rate)
+        self.iteration = 0
+        self.losses: list[float] = []
+        self.graph = ops.StepGraph(pb, balls, deform, frame_t, sensors, measured) if use_graph else None
+        if self.graph is None:
+            self.y = torch.empty_like(measured)
+            self.r = torch.empty_like(measured)
+            self.L = torch.empty((), dtype=torch.float64, device=measured.device)
+            self.gb = torch.empty_like(balls)
+            self.gd = torch.empty_like(deform) if deform is not None else None
+        gb = self.graph.grad_balls if self.graph is not None else self.gb
+        gd = self.graph.grad_deform if self.graph is not None else self.gd
+        self.groups = [(balls[0:3], gb[0:3], self.lrs[0]), (balls[3], gb[3], self.lrs[1]),
+                       (balls[4], gb[4], self.lrs[2])]
+        if deform is not None:
+            self.groups.append((deform, gd, self.lrs[3]))
+        self.moments = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in self.groups]
+
+    # ---- one iteration
+    def _loss_tensor(self):
+        return self.graph.loss if self.graph is not None else self.L
+
+    def step(self) -> None:
+        if self.graph is not None:
+            self.graph.run()
+        else:
+            ops.forward(self.pb, self.balls, self.deform, self.frame_t, self.sensors, out=self.y)
+            ops.loss(self.pb, self.y, self.measured, residual=self.r, loss_out=self.L)
+            ops.adjoint(self.pb, self.balls, self.deform, self.frame_t, self.sensors, self.r,
+                        grad_balls=self.gb, grad_deform=self.gd)
+        factor = step_decay(self.iteration, self.decay_step, self.decay_rate)
+        t = self.iteration + 1
+        for (p, g, lr), (m, v) in zip(self.groups, self.moments):
+            ops.adam_(p, g, m, v, lr * factor, t)
+        self.iteration += 1
+
+    def run(self, n: int, on_iter=None) -> list[float]:
+        """n iterations; returns the loss before each update (one host sync per iteration)."""
+        out = []
+        for _ in range(n):
+            self.step()
+            L = float(self._loss_tensor().item())
+            self.losses.append(L)
+            out.append(L)
+            if on_iter is not None:
+                on_iter(self.iteration, L)
+        return out
+
+    def close(self) -> None:
+        if self.graph is not None:
+            self.graph.close()
+            self.graph = None
+
+    # ---- checkpoint
+    def state_arrays(self) -> dict:
+        st = {"iteration": np.array(self.iteration, dtype=np.int64),
+              "losses": np.array(self.losses, dtype=np.float64),
+              "lrs": np.array(self.lrs, dtype=np.float64),
+              "decay": np.array([self.decay_step, self.decay_rate], dtype=np.float64),
+              "balls": self.balls.detach().cpu().numpy()}
+        if self.deform is not None:
+            st["deform"] = self.deform.detach().cpu().numpy()
+        for i, (m, v) in enumerate(self.moments):
+            st[f"m{i}"] = m.detach().cpu().numpy()
+            st[f"v{i}"] = v.detach().cpu().numpy()
+        return st
+
+    def save(self, path: str) -> None:
+        torch.cuda.synchronize()
+        np.savez(path, **self.state_arrays())
+
+    def load(self, path: str) -> None:
+        """Restore parameters, moments, iteration count and loss history saved by save()."""
+        with np.load(path, allow_pickle=False) as z:
+            if z["balls"].shape != tuple(self.balls.shape):
+                raise ValueError("checkpoint does not match this problem's ball count")
+            self.balls.copy_(torch.from_numpy(z["balls"]))
+            if self.deform is not None:
+                if "deform" not in z or z["deform"].shape != tuple(self.deform.shape):
+                    raise ValueError("checkpoint does not match this problem's coefficients")
+                self.deform.copy_(torch.from_numpy(z["deform"]))
+            for i, (m, v) in enumerate(self.moments):
+                m.copy_(torch.from_numpy(z[f"m{i}"]))
+                v.copy_(torch.from_numpy(z[f"v{i}"]))
+            self.iteration = int(z["iteration"])
+            self.losses = [float(x) for x in z["losses"]]
+        torch.cuda.synchronize()
+
+
+def _per_frame_static(wl, balls_np, deform_np):
+    """Per-frame static attributes of a Fourier-deformed scene (Eq. 1 with the Fourier
+    series, additive position, scaled size and pressure), materialised in FP64 and stored
+    as FP32: the input of the frame-by-frame path."""
+    b = balls_np.astype(np.float64)
+    D = deform_np.astype(np.float64)
+    for f in range(wl.n_frames):
+        t = float(wl.frame_t[f])
+        h = sum(D[:, 2 * (k - 1)] * np.cos(2 * np.pi * k * t) + D[:, 2 * (k - 1) + 1] * np.sin(2 * np.pi * k * t)
+                for k in range(1, wl.n_terms + 1))
+        x = b.copy()
+        x[0:3] += h[0:3]
+        x[3:5] *= 1.0 + h[3:5]
+        yield np.ascontiguousarray(x.astype(np.float32))
+
+
+def large_ir(iters: int = 200, per_frame_iters: int = 3, tuning=None, n_balls: int = 1_000_000,
+             n_frames: int = 32, n_sensors: int = 2048, checkpoint: str | None = None,
+             resume: str | None = None, log=print) -> dict:
+    """The large 4D IR run (see module docstring); returns the result record."""
+    from . import binding, synth, tune
+
+    dev = "cuda:0"
+    t_setup = time.perf_counter()
+    wl = synth.workload_large_ir(n_balls=n_balls, n_frames=n_frames, n_sensors=n_sensors)
+    pb, gt_balls, gt_deform, ft, sens = ops.to_device(wl, dev)
+    gt_balls, gt_deform, _ = ops.apply_order(pb, gt_balls, gt_deform)
+    if tuning is None:
+        choice = tune.autotune(pb, gt_balls, gt_deform, ft, sens, cache=None)
+    else:
+        choice = list(tuning)
+        for key, val in zip((binding.SB_TUNE_FWD_COLUMN, binding.SB_TUNE_ADJ_OCCUPANCY,
+                             binding.SB_TUNE_ADJ_ITEMS), choice):
+            binding.tune(key, val)
+    # measured signals: the ground-truth 4D scene (ground-truth coefficients)
+    measured = ops.forward(pb, gt_balls, gt_deform, ft, sens)
+    ops.check()
+    # initial guess: perturbed base attributes, zero deformation coefficients
+    balls = torch.from_numpy(synth.perturbed(gt_balls.cpu().numpy(), 10)).to(dev)
+    deform = torch.zeros_like(gt_deform)
+    del gt_deform
+    torch.cuda.synchronize()
+    log(f"[ir] setup {time.perf_counter() - t_setup:.1f} s: {wl.n_balls} balls, {wl.n_frames} frames, "
+        f"{wl.n_sensors} sensors, {wl.n_samples} samples, tuning {choice}")
+
+    torch.cuda.reset_peak_memory_stats()
+    free0, total = torch.cuda.mem_get_info()
+    loop = IRLoop(pb, balls, deform, ft, sens, measured)
+    if resume:
+        loop.load(resume)
+        log(f"[ir] resumed at iteration {loop.iteration}")
+    min_free = [torch.cuda.mem_get_info()[0]]
+    times = []
+
+    def on_iter(i, L):
+        times.append(time.perf_counter())
+        if i % 10 == 0 or i == 1:
+            min_free[0] = min(min_free[0], torch.cuda.mem_get_info()[0])
+            log(f"[ir] iteration {i}: loss {L:.6e}")
+
+    todo = max(0, iters - loop.iteration)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop.run(todo, on_iter)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    peak_torch = torch.cuda.max_memory_allocated()
+    ops.check()
+    if checkpoint:
+        loop.save(checkpoint)
+    losses = list(loop.losses)
+    loop.close()
+    # steady-state ms/iteration: skip the first iteration (graph warm-up)
+    steady = (times[-1] - times[0]) / (len(times) - 1) * 1e3 if len(times) > 1 else elapsed * 1e3
+    pairs = pb.pairs()
+    rec = {"workload": wl.name, "balls": wl.n_balls, "frames": wl.n_frames, "sensors": wl.n_sensors,
+           "samples": wl.n_samples, "iterations": loop.iteration, "tuning": choice,
+           "ms_per_iter": round(steady, 2), "gpairs_per_s": round(pairs / (steady * 1e-3) / 1e9, 3),
+           "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
+           "loss_curve": [losses[i] for i in range(0, len(losses), 10)],
+           "peak_mem_mb_torch": round(peak_torch / 2**20, 1),
+           "peak_mem_mb_device": round((total - min_free[0]) / 2**20, 1),
+           "device_mem_before_mb": round((total - free0) / 2**20, 1)}
+    del loop, balls, deform
+    torch.cuda.empty_cache()
+
+    if per_frame_iters > 0:
+        rec["per_frame"] = _per_frame_path(wl, pb, gt_balls, ft, sens, measured, per_frame_iters, log)
+    return rec
+
+
+def _per_frame_path(wl, pb, balls, ft, sens, measured, iters, log) -> dict:
+    """Frame-by-frame path: every frame an independent static scene with its own
+    materialised attributes, one forward, loss, adjoint and Adam per frame."""
+    from .binding import Problem
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    B = wl.n_balls
+    pf = Problem(wl.kernel, 0, 0, 0, wl.n_sensors, wl.n_samples, wl.c, wl.fs, wl.t0,
+                 np.array([0, B]), np.array([0, 1]))
+    t0 = torch.zeros(1, dtype=torch.float32, device="cuda")
+    # frames at the zero-coefficient start, which the batched run also starts from
+    zero = np.zeros((5, 2 * wl.n_terms, B), dtype=np.float32)
+    fb = [torch.from_numpy(x).cuda() for x in _per_frame_static(wl, balls.cpu().numpy(), zero)]
+    fy = torch.empty((1, wl.n_sensors, wl.n_samples), dtype=torch.float32, device="cuda")
+    fr = torch.empty_like(fy)
+    fL = torch.empty((), dtype=torch.float64, device="cuda")
+    fg = [torch.empty_like(x) for x in fb]
+    fstate = [[(torch.zeros_like(x[0:3]), torch.zeros_like(x[0:3])), (torch.zeros_like(x[3]), torch.zeros_like(x[3])),
+               (torch.zeros_like(x[4]), torch.zeros_like(x[4]))] for x in fb]
+
+    def one(it):
+        for f in range(wl.n_frames):
+            ops.forward(pf, fb[f], None, t0, sens, out=fy)
+            ops.loss(pf, fy, measured[f:f + 1], residual=fr, loss_out=fL)
+            ops.adjoint(pf, fb[f], None, t0, sens, fr, grad_balls=fg[f])
+            x, g = fb[f], fg[f]
+            for (p, gg, lr), (m, v) in zip(((x[0:3], g[0:3], LR_POS), (x[3], g[3], LR_R), (x[4], g[4], LR_P)),
+                                           fstate[f]):
+                ops.adam_(p, gg, m, v, lr, it + 1)
+
+    one(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for it in range(1, iters + 1):
+        one(it)
+        torch.cuda.synchronize()
+        log(f"[ir] per-frame iteration {it}")
+    ms = (time.perf_counter() - t) / iters * 1e3
+    ops.check()
+    rec = {"ms_per_iter": round(ms, 2), "iterations_timed": iters,
+           "peak_mem_mb_torch": round(torch.cuda.max_memory_allocated() / 2**20, 1)}
+    del fb, fg, fstate
+    torch.cuda.empty_cache()
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--per-frame-iters", type=int, default=3)
+    ap.add_argument("--balls", type=int, default=1_000_000)
+    ap.add_argument("--frames", type=int, default=32)
+    ap.add_argument("--sensors", type=int, default=2048)
+    ap.add_argument("--tuning", default=None, help="COLUMN,OCCUPANCY,ITEMS instead of autotuning")
+    ap.add_argument("--checkpoint", default=None, help="save the state here at the end (.npz)")
+    ap.add_argument("--resume", default=None, help="continue from a saved state (.npz)")
+    args = ap.parse_args()
+    tuning = [int(x) for x in args.tuning.split(",")] if args.tuning else None
+    rec = large_ir(args.iters, args.per_frame_iters, tuning, args.balls, args.frames, args.sensors,
+                   args.checkpoint, args.resume, log=lambda s: print(s, flush=True))
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

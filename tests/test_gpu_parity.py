@@ -236,35 +236,68 @@ def test_nonfinite_ball_is_skipped_and_flagged():
     assert rel_l2(y.cpu().numpy(), ref) <= SIG_TOL
 
 
-# ---------------------------------------------------------------- full sizes, sampled sensors
+# ---------------------------------------------------------------- full sizes, sampled outputs
+# The GPU runs the whole problem (every ball, sensor and frame, default knobs);
+# the oracle computes the sampled (frame, sensor) rows.  For the adjoint the
+# GPU's residual is zero outside those rows, so its gradient equals the oracle
+# adjoint of the sub-problem made of just those rows.
+def _full_size_sampled(wl, s_step, f_step, seed):
+    import torch
+    from paper_2412_03898_amd import ops
+    F = wl.n_frames
+    s_idx = np.arange(0, wl.n_sensors, s_step)
+    if len(wl.ball_offset) == 2:
+        f_idx = np.arange(0, F, f_step)
+        sub = with_(wl, sensors=wl.sensors[:, s_idx].copy(), frame_t=wl.frame_t[f_idx].copy(),
+                    frame_offset=np.array([0, len(f_idx)]), n_frames=len(f_idx))
+    else:                       # batch of scenes: every frame of every scene
+        f_idx = np.arange(F)
+        sub = with_(wl, sensors=wl.sensors[:, s_idx].copy())
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    fi = torch.from_numpy(f_idx).cuda()[:, None]
+    si = torch.from_numpy(s_idx).cuda()[None, :]
+    y = ops.forward(pb, balls, deform, ft, sens)
+    assert ops.check() == 0
+    got = y[fi, si].cpu().numpy().astype(np.float64)
+    del y
+    ref = oracle.forward(sub)
+    err = rel_l2(got, ref)
+    _say(f"forward sampled rel-L2 {err:.3e} ({len(f_idx)} frames x {len(s_idx)} sensors)")
+    assert err <= SIG_TOL
+    rng = np.random.default_rng(seed)
+    rows = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
+    res = torch.zeros((F, wl.n_sensors, wl.n_samples), dtype=torch.float32, device="cuda")
+    res[fi, si] = torch.from_numpy(rows).cuda()
+    gb, gd = ops.adjoint(pb, balls, deform, ft, sens, res)
+    assert ops.check() == 0
+    got_g = (gb.cpu().numpy().astype(np.float64), None if gd is None else gd.cpu().numpy().astype(np.float64))
+    del res, gb, gd
+    assert_grads(sub, got_g, oracle.adjoint(sub, rows.astype(np.float64)))
+
+
 def test_vessel_static_full_size_sampled():
     wl = synth.apply_order(synth.workload_vessel_static())
     _say(f"vessel static full B={wl.n_balls} S={wl.n_sensors} T={wl.n_samples}")
-    y, flags = gpu_forward(wl)
-    assert flags == 0
-    sub = with_(wl, sensors=wl.sensors[:, ::16].copy())
-    ref = oracle.forward(sub)
-    err = rel_l2(y[:, ::16], ref)
-    _say(f"forward sampled rel-L2 {err:.3e}")
-    assert err <= SIG_TOL
-    rng = np.random.default_rng(6)
-    res = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
-    assert_grads(sub, gpu_adjoint(sub, res), oracle.adjoint(sub, res.astype(np.float64)))
+    _full_size_sampled(wl, 16, 1, 6)
 
 
 def test_vessel_4d_full_size_sampled():
     wl = synth.apply_order(synth.workload_vessel_4d())
     _say(f"vessel 4d full B={wl.n_balls} S={wl.n_sensors} F={wl.n_frames} T={wl.n_samples}")
-    y, flags = gpu_forward(wl)
-    assert flags == 0
-    sub = with_(wl, sensors=wl.sensors[:, ::16].copy())
-    ref = oracle.forward(sub)
-    err = rel_l2(y[:, ::16], ref)
-    _say(f"forward sampled rel-L2 {err:.3e}")
-    assert err <= SIG_TOL
-    rng = np.random.default_rng(7)
-    res = (rng.normal(size=ref.shape) * np.abs(ref).max()).astype(np.float32)
-    assert_grads(sub, gpu_adjoint(sub, res), oracle.adjoint(sub, res.astype(np.float64)))
+    _full_size_sampled(wl, 16, 1, 7)
+
+
+def test_uneven_batch_full_size_sampled():
+    wl = synth.apply_order(synth.workload_uneven_batch())
+    _say(f"uneven batch full: scenes={len(wl.ball_offset) - 1} B={wl.n_balls} F={wl.n_frames} "
+         f"S={wl.n_sensors} T={wl.n_samples}")
+    _full_size_sampled(wl, 64, 1, 11)
+
+
+def test_large_ir_scene_full_size_sampled():
+    wl = synth.apply_order(synth.workload_large_ir())
+    _say(f"large 4D full B={wl.n_balls} F={wl.n_frames} S={wl.n_sensors} T={wl.n_samples}")
+    _full_size_sampled(wl, 128, 8, 12)
 
 
 # ---------------------------------------------------------------- ordering (performance only)

@@ -191,6 +191,51 @@ def ir_4d_comparison(steps, warmup):
             "peak_mem_mb_batched": round(mem_batched, 1), "peak_mem_mb_per_frame": round(mem_frames, 1)}
 
 
+def uneven_batch_timing(steps, warmup):
+    """GPairs/s of forward + adjoint on the uneven batch: 8 independent 4D vessel scenes
+    (ball counts log-uniform in 1e4..4e5, 4, 8, 16 or 32 frames each, Fourier K = 2)
+    sharing one 1,024-sensor hemisphere, 4,096 samples, in one forward and one adjoint
+    launch per step (with loss and Adam)."""
+    import torch
+    from paper_2412_03898_amd import ops, synth, tune
+    wl = synth.workload_uneven_batch()
+    pb, balls, deform, ft, sens = ops.to_device(wl, "cuda:0")
+    balls, deform, _ = ops.apply_order(pb, balls, deform)
+    choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
+    pert = torch.from_numpy(synth.perturbed(balls.cpu().numpy(), 1)).cuda()
+    d = ops.forward(pb, pert, deform, ft, sens)
+    del pert
+    y, r = torch.empty_like(d), torch.empty_like(d)
+    L = torch.empty((), dtype=torch.float64, device="cuda")
+    gb, gd = torch.empty_like(balls), torch.empty_like(deform)
+    groups = [(balls[0:3], gb[0:3], LR_POS), (balls[3], gb[3], LR_R), (balls[4], gb[4], LR_P), (deform, gd, LR_DEF)]
+    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in groups]
+    it = [0]
+
+    def step():
+        ops.forward(pb, balls, deform, ft, sens, out=y)
+        ops.loss(pb, y, d, residual=r, loss_out=L)
+        ops.adjoint(pb, balls, deform, ft, sens, r, grad_balls=gb, grad_deform=gd)
+        it[0] += 1
+        for (p, g, lr), (m, v) in zip(groups, state):
+            ops.adam_(p, g, m, v, lr, it[0])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / steps * 1e3
+    flags = ops.check()
+    pairs = pb.pairs()
+    return {"workload": wl.name, "scenes": len(wl.ball_offset) - 1, "balls": wl.n_balls,
+            "frames": wl.n_frames, "sensors": wl.n_sensors, "samples": wl.n_samples,
+            "pairs_per_pass": pairs, "tuning": list(choice), "ms_per_step": round(ms, 3),
+            "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 3), "device_flags": flags}
+
+
 def cpu_baseline(wl, d_np):
     """Time the FP64 oracle on the host: one forward, loss and adjoint of the same workload."""
     import numpy as np
@@ -219,6 +264,7 @@ def main():
     ap.add_argument("--workload", default="vessel-single-frame", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-4d", action="store_true", help="skip the 4D batched vs per-frame comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven 8-scene batch timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (a known amount of HBM traffic for "
                          "scaling memory counters)")
@@ -321,6 +367,12 @@ def main():
     per_kernel = {k: (ms / n if n else None) for k, (ms, n) in kt.items()}
     dom = max(("forward", "adjoint"), key=lambda k: per_kernel[k] or 0.0)
     achieved = fm[dom] / (per_kernel[dom] * 1e-3) / 1e12
+    # HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE /
+    # WRITE_SIZE record of this workload and instance (null once its sources change)
+    from paper_2412_03898_amd import profsum
+    instance = (f"forward_kernel<4, 256, {choice[0]}, 0>" if dom == "forward"
+                else f"adjoint_uniform_kernel<{4 if wl.basis == 1 and wl.n_terms == 2 else 0}, {choice[1]}>")
+    traffic = profsum.traffic_for(instance, wl.name)
     out = {
         "metric": "GPairs/s fwd+adjoint (ball\u00b7sensor\u00b7frame) and ms/IR iteration vs per-frame path",
         "value": round(value, 4),
@@ -342,7 +394,7 @@ def main():
                               "adjoint_items": choice[2]}},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic, "traffic_unit": "B/launch",
                      "ops_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3)},
         "kernel_ms": {k: (round(v, 4) if v is not None else None) for k, v in per_kernel.items()},
         "graph_ms_per_step": None if ms_graph is None else round(ms_graph, 4),
@@ -350,6 +402,8 @@ def main():
     }
     if not args.no_4d:
         out["ir_4d"] = ir_4d_comparison(max(3, args.steps // 4), 2)
+    if not args.no_batch:
+        out["uneven_batch"] = uneven_batch_timing(3, 1)
     if not args.no_cpu_baseline:
         # the oracle's timing does not depend on the measured values: zeros stand in for them
         d_np = np.zeros((wl.n_frames, wl.n_sensors, wl.n_samples))

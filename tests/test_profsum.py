@@ -1,0 +1,36 @@
+"""The bench's HBM traffic figure comes from a committed counter record and is
+withheld once the kernel's sources differ from the ones that were profiled."""
+
+import json
+
+from paper_2412_03898_amd import profsum
+
+
+def test_traffic_record_follows_sources(tmp_path, monkeypatch):
+    root = tmp_path
+    (root / "profiles").mkdir()
+    src = root / "k.hip"
+    src.write_text("kernel v1\n")
+    monkeypatch.setattr(profsum, "ROOT", str(root))
+    monkeypatch.setattr(profsum, "PROFILES", str(root / "profiles"))
+    rec = {"kernel": "k<1>", "workload": "w", "bytes_per_launch": 1234, "sources": ["k.hip"],
+           "source_sha256": profsum.source_digest(["k.hip"])}
+    (root / "profiles" / "k_w_traffic.json").write_text(json.dumps(rec))
+    assert profsum.traffic_for("k<1>", "w") == 1234
+    assert profsum.traffic_for("k<2>", "w") is None
+    assert profsum.traffic_for("k<1>", "other") is None
+    src.write_text("kernel v2\n")
+    assert profsum.traffic_for("k<1>", "w") is None
+
+
+def test_committed_record_is_consistent():
+    """Every committed record names existing sources and scales its counters as stated."""
+    import os
+    for name in os.listdir(profsum.PROFILES):
+        if name.endswith("_traffic.json"):
+            with open(os.path.join(profsum.PROFILES, name)) as f:
+                rec = json.load(f)
+            want = rec["fetch_scale"] * rec["fetch_kib"] * 1024 + rec["write_scale"] * rec["write_kib"] * 1024
+            assert abs(rec["bytes_per_launch"] - want) <= 0.05 * 1024 * (rec["fetch_scale"] + rec["write_scale"])
+            for s in rec["sources"]:
+                assert os.path.exists(os.path.join(profsum.ROOT, s))

@@ -236,6 +236,34 @@ def uneven_batch_timing(steps, warmup):
             "gpairs_s": round(pairs / (ms * 1e-3) / 1e9, 3), "device_flags": flags}
 
 
+def voxel_map_timing(pb, balls, deform, reps=5):
+    """Point cloud -> voxel grid -> maximum amplitude projections for the bench scene:
+    a 40 mm cube of 0.1 mm voxels (400^3, 256 MB) at frame time 0; mean ms of
+    slingbag_voxelize and of slingbag_map (all three projections)."""
+    import torch
+    from paper_2412_03898_amd import ops
+    g = (400, 400, 400, -0.01995, -0.01995, -0.01995, 0.1e-3)
+    vol = ops.voxelize(pb, balls, deform, 0.0, g)
+    ops.map_projections(vol)
+    ops.check()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        ops.voxelize(pb, balls, deform, 0.0, g, out=vol)
+    e[1].record()
+    for _ in range(reps):
+        ops.map_projections(vol)
+    e[2].record()
+    torch.cuda.synchronize()
+    ops.check()
+    tv, tm = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    nvox = 400 ** 3
+    del vol
+    return {"grid": [400, 400, 400], "pitch_mm": 0.1, "balls": int(balls.shape[1]),
+            "voxelize_ms": round(tv, 3), "map_ms": round(tm, 3),
+            "map_read_gb_s": round(3 * nvox * 4 / (tm * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(wl, d_np):
     """Time the FP64 oracle on the host: one forward, loss and adjoint of the same workload."""
     import numpy as np
@@ -265,6 +293,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-4d", action="store_true", help="skip the 4D batched vs per-frame comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven 8-scene batch timing")
+    ap.add_argument("--no-voxel", action="store_true", help="skip the voxel grid / MAP timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (a known amount of HBM traffic for "
                          "scaling memory counters)")
@@ -404,6 +433,8 @@ def main():
         out["ir_4d"] = ir_4d_comparison(max(3, args.steps // 4), 2)
     if not args.no_batch:
         out["uneven_batch"] = uneven_batch_timing(3, 1)
+    if not args.no_voxel:
+        out["voxel_map"] = voxel_map_timing(pb, balls, deform)
     if not args.no_cpu_baseline:
         # the oracle's timing does not depend on the measured values: zeros stand in for them
         d_np = np.zeros((wl.n_frames, wl.n_sensors, wl.n_samples))

@@ -239,6 +239,37 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
 int slingbag_timing(int enable);
 int slingbag_timing_read(double* total_ms, int64_t* launches);
 
+/* ---- point cloud -> voxel grid and maximum amplitude projections ----
+ * Sec. 2.1 and Sec. 3: the reconstruction is viewed by converting the point
+ * cloud into a voxel grid and projecting it (MAP images in the XY, YZ and XZ
+ * planes).  The grid holds the model's initial pressure p0(x) = sum over balls
+ * of P_f phi(|x - x_f|) sampled at voxel centres, phi = 1[d <= R_f] for the
+ * uniform sphere (the inside test taken in FP64) or exp(-d^2 / (2 R_f^2)) for
+ * the Gaussian ball (cut at 6 R_f). */
+typedef struct sb_grid {
+    int32_t nx, ny, nz;  /* voxels per axis, each >= 1; nx*ny*nz <= 2^31 */
+    int32_t reserved;    /* must be 0 */
+    double  x0, y0, z0;  /* centre of voxel (0, 0, 0), metres, finite */
+    double  h;           /* voxel pitch, metres, > 0; voxel (i,j,k) is centred at (x0+i h, y0+j h, z0+k h) */
+} sb_grid;
+
+/* Voxelise one scene at frame time t: volume[k][j][i] (device, FP32, nz*ny*nx,
+ * caller-owned, every entry overwritten) = p0 at the centre of voxel (i,j,k)
+ * for the n_balls balls [5][n_balls] (device) deformed by Eq. 1 at t with the
+ * coefficients deform [5][M][n_balls] (device; NULL only for SB_BASIS_STATIC).
+ * cfg supplies kernel, basis, pos_mode and n_terms (its sensor, sample and
+ * time fields are ignored).  Balls with non-finite or invalid attributes are
+ * skipped and set SB_FLAG_NONFINITE.  n_balls may be 0 (zero volume).
+ * Scratch: none beyond the per-device flag word. */
+int slingbag_voxelize(const sb_config* cfg, const sb_grid* grid, int64_t n_balls, const float* balls,
+                      const float* deform, float t, float* volume, void* stream);
+
+/* Maximum amplitude projections of a volume [nz][ny][nx] (device): map_xy[j][i]
+ * = max over k, map_yz[k][j] = max over i, map_xz[k][i] = max over j (device,
+ * FP32, caller-owned; any of the three may be NULL to skip it). */
+int slingbag_map(const sb_grid* grid, const float* volume, float* map_xy, float* map_yz,
+                 float* map_xz, void* stream);
+
 /* Message for the last non-OK status returned on the calling host thread. */
 const char* slingbag_last_error(void);
 

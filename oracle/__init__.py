@@ -68,6 +68,10 @@ def _load():
         lib.sbo_loss.restype = ctypes.c_double
         lib.sbo_deformed.argtypes = [P(Problem), ctypes.c_int, i64, i64, d, d, d, ctypes.c_int64, d]
         lib.sbo_deformed.restype = ctypes.c_int
+        lib.sbo_voxelize.argtypes = [ctypes.c_int, ctypes.c_int64, d, d, d, d, d, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int32, d]
+        lib.sbo_voxelize.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -193,3 +197,37 @@ def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** step)
     vhat = v / (1.0 - beta2 ** step)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def voxelize(kernel: int, attrs, grid, gauss_window: float = 10.0, n_threads: int = 0) -> np.ndarray:
+    """Voxel grid [nz][ny][nx] of the initial pressure of balls with (deformed) attributes
+    attrs [5][B] (x, y, z, R, P): sum of P phi(d) at voxel centres, phi = 1[d <= R]
+    (uniform sphere) or exp(-d^2 / 2R^2) (Gaussian ball).  grid = (nx, ny, nz, x0, y0, z0, h)
+    with voxel (i, j, k) centred at (x0 + i h, y0 + j h, z0 + k h)."""
+    lib = _load()
+    a = _f64(attrs)
+    nx, ny, nz, x0, y0, z0, h = grid
+    vol = np.empty((int(nz), int(ny), int(nx)))
+    st = lib.sbo_voxelize(int(kernel), a.shape[1], _ptr(np.ascontiguousarray(a[0])), _ptr(np.ascontiguousarray(a[1])),
+                          _ptr(np.ascontiguousarray(a[2])), _ptr(np.ascontiguousarray(a[3])),
+                          _ptr(np.ascontiguousarray(a[4])), int(nx), int(ny), int(nz), float(x0), float(y0),
+                          float(z0), float(h), float(gauss_window), int(n_threads), _ptr(vol))
+    _check(st, "oracle voxelize")
+    return vol
+
+
+def voxelize_scene(wl, t: float, grid, balls=None, deform=None, **kw) -> np.ndarray:
+    """voxelize() of a single-scene workload's balls deformed by Eq. 1 at frame time t."""
+    import types
+    B = (wl.balls if balls is None else balls).shape[1]
+    one = types.SimpleNamespace(**{**vars(wl), "frame_t": np.array([t], dtype=np.float32),
+                                   "ball_offset": np.array([0, B]), "frame_offset": np.array([0, 1])})
+    attrs = deformed(one, 0, balls=balls, deform=deform)
+    return voxelize(wl.kernel, attrs, grid, **kw)
+
+
+def maps(vol):
+    """Maximum amplitude projections of vol [nz][ny][nx]: (xy [ny][nx] = max over z,
+    yz [nz][ny] = max over x, xz [nz][nx] = max over y)."""
+    v = np.asarray(vol)
+    return v.max(axis=0), v.max(axis=2), v.max(axis=1)

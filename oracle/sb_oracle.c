@@ -364,3 +364,60 @@ int sbo_adjoint(const sbo_problem* p, int n_scenes, const int64_t* ball_offset,
     }
     return err;
 }
+
+/*
+ * Voxel grid of the initial pressure (the point cloud viewed as an image,
+ * Sec. 2.1 and the maximum amplitude projections of Sec. 3).
+ *
+ *  vol[k][j][i] = sum over balls b of P_b phi(d), d = distance from the centre
+ *  of voxel (i,j,k), (x0 + i h, y0 + j h, z0 + k h), to the ball centre;
+ *  phi = 1[d <= R_b] (uniform sphere) or exp(-d^2 / (2 R_b^2)) (Gaussian ball,
+ *  evaluated out to `gauss_window` R_b; <= 0 means every voxel).
+ *  Inputs are the (already deformed) attributes in FP64, one array per
+ *  attribute.  Planes k are independent, so they are split over threads; each
+ *  voxel's sum runs over the balls in order.
+ */
+int sbo_voxelize(int kernel, int64_t n, const double* x, const double* y, const double* z,
+                 const double* R, const double* P, int32_t nx, int32_t ny, int32_t nz,
+                 double x0, double y0, double z0, double h, double gauss_window, int32_t n_threads,
+                 double* vol) {
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || n < 0) return SBO_ERR_ARG;
+    memset(vol, 0, sizeof(double) * (size_t)nx * ny * nz);
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < nz; ++k) {
+        const double zc = fma((double)k, h, z0);
+        for (int64_t b = 0; b < n; ++b) {
+            /* balls with non-finite or invalid attributes contribute nothing */
+            if (!isfinite(x[b]) || !isfinite(y[b]) || !isfinite(z[b]) || !isfinite(R[b]) || !isfinite(P[b]) ||
+                !(R[b] > 0.0) || !(P[b] >= 0.0))
+                continue;
+            const double reach = (kernel == 0) ? R[b]
+                               : (gauss_window > 0.0 ? gauss_window * R[b] : INFINITY);
+            const double dz = zc - z[b];
+            if (fabs(dz) > reach) continue;
+            /* every (i, j) whose centre is within reach in x and y */
+            int64_t i0 = 0, i1 = nx - 1, j0 = 0, j1 = ny - 1;
+            if (isfinite(reach)) {
+                const double lo_i = floor((x[b] - reach - x0) / h) - 1, hi_i = ceil((x[b] + reach - x0) / h) + 1;
+                const double lo_j = floor((y[b] - reach - y0) / h) - 1, hi_j = ceil((y[b] + reach - y0) / h) + 1;
+                if (lo_i > i0) i0 = (int64_t)lo_i;
+                if (hi_i < i1) i1 = (int64_t)hi_i;
+                if (lo_j > j0) j0 = (int64_t)lo_j;
+                if (hi_j < j1) j1 = (int64_t)hi_j;
+            }
+            for (int64_t j = j0; j <= j1; ++j) {
+                const double dy = fma((double)j, h, y0) - y[b];
+                for (int64_t i = i0; i <= i1; ++i) {
+                    const double dx = fma((double)i, h, x0) - x[b];
+                    const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    double v;
+                    if (kernel == 0) v = (d2 <= R[b] * R[b]) ? P[b] : 0.0;
+                    else v = (d2 <= reach * reach) ? P[b] * exp(-d2 / (2.0 * R[b] * R[b])) : 0.0;
+                    vol[((int64_t)k * ny + j) * nx + i] += v;
+                }
+            }
+        }
+    }
+    return SBO_OK;
+}

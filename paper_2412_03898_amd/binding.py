@@ -50,6 +50,12 @@ class Batch(ctypes.Structure):
                 ("frame_offset", ctypes.POINTER(ctypes.c_int64))]
 
 
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("z0", ctypes.c_double), ("h", ctypes.c_double)]
+
+
 _lib = None
 
 _VP = ctypes.c_void_p
@@ -73,6 +79,9 @@ _SIGS = {
     "slingbag_tune_get": [ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "slingbag_timing": [ctypes.c_int],
     "slingbag_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "slingbag_voxelize": [ctypes.POINTER(Config), ctypes.POINTER(Grid), ctypes.c_int64, _VP, _VP, ctypes.c_float,
+                          _VP, _VP],
+    "slingbag_map": [ctypes.POINTER(Grid), _VP, _VP, _VP, _VP, _VP],
     "slingbag_last_error": [],
     "slingbag_version": [],
 }
@@ -199,6 +208,21 @@ def order(pb: Problem, balls: int, perm: int, stream: int = 0):
 
 def permute(src: int, dst: int, rows: int, n: int, perm: int, stream: int = 0):
     _check(load().slingbag_permute(src, dst, rows, n, perm, stream))
+
+
+def make_grid(nx: int, ny: int, nz: int, x0: float, y0: float, z0: float, h: float) -> Grid:
+    return Grid(int(nx), int(ny), int(nz), 0, float(x0), float(y0), float(z0), float(h))
+
+
+def voxelize(kernel: int, basis: int, pos_mode: int, n_terms: int, grid: Grid, n_balls: int, balls: int,
+             deform: int, t: float, volume: int, stream: int = 0):
+    cfg = Config(int(kernel), int(basis), int(pos_mode), int(n_terms), 1, 1, 1.0, 1.0, 0.0)
+    _check(load().slingbag_voxelize(ctypes.byref(cfg), ctypes.byref(grid), int(n_balls), balls, deform,
+                                    float(t), volume, stream))
+
+
+def map_projections(grid: Grid, volume: int, xy: int, yz: int, xz: int, stream: int = 0):
+    _check(load().slingbag_map(ctypes.byref(grid), volume, xy, yz, xz, stream))
 
 
 def check(stream: int = 0) -> int:

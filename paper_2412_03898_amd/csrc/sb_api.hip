@@ -64,7 +64,8 @@ struct Shape {
     int M = 0;
 };
 
-static int validate_config(const sb_config* cfg, Shape& sh) {
+// kernel, basis, position mode and term count (the ball model); M = coefficients per attribute
+static int validate_model(const sb_config* cfg, int64_t& M) {
     if (!cfg) return fail(SB_ERR_INVALID_ARG, "cfg is NULL");
     if (cfg->kernel != SB_KERNEL_UNIFORM && cfg->kernel != SB_KERNEL_GAUSS)
         return fail(SB_ERR_INVALID_ARG, "unknown kernel %d", cfg->kernel);
@@ -77,6 +78,15 @@ static int validate_config(const sb_config* cfg, Shape& sh) {
     if (cfg->basis == SB_BASIS_GAUSS && (cfg->n_terms < 1 || cfg->n_terms > SB_MAX_GAUSS_BASES))
         return fail(SB_ERR_SHAPE, "n_terms %d outside 1..%d for the Gaussian basis", cfg->n_terms,
                     SB_MAX_GAUSS_BASES);
+    M = cfg->basis == SB_BASIS_FOURIER ? 2 * cfg->n_terms
+      : cfg->basis == SB_BASIS_GAUSS   ? 3 * cfg->n_terms : 0;
+    return SB_OK;
+}
+
+static int validate_config(const sb_config* cfg, Shape& sh) {
+    int64_t M = 0;
+    const int st = validate_model(cfg, M);
+    if (st) return st;
     if (cfg->n_sensors < 1) return fail(SB_ERR_SHAPE, "n_sensors must be >= 1 (got %d)", cfg->n_sensors);
     if (cfg->n_samples < 1 || cfg->n_samples > (1 << 28))
         return fail(SB_ERR_SHAPE, "n_samples must be in 1..2^28 (got %d)", cfg->n_samples);
@@ -85,8 +95,7 @@ static int validate_config(const sb_config* cfg, Shape& sh) {
     if (!(cfg->c > 0.0) || !(cfg->fs > 0.0)) return fail(SB_ERR_INVALID_ARG, "c and fs must be > 0");
     sh.S = cfg->n_sensors;
     sh.T = cfg->n_samples;
-    sh.M = cfg->basis == SB_BASIS_FOURIER ? 2 * cfg->n_terms
-         : cfg->basis == SB_BASIS_GAUSS   ? 3 * cfg->n_terms : 0;
+    sh.M = M;
     return SB_OK;
 }
 
@@ -263,7 +272,7 @@ using namespace sb;
 
 extern "C" {
 
-int slingbag_version(void) { return (1 << 16) | 0; }
+int slingbag_version(void) { return (1 << 16) | 1; }
 
 const char* slingbag_last_error(void) { return g_last_error.c_str(); }
 
@@ -372,6 +381,65 @@ int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n
     hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
     time_mark(kTimeAdam, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adam kernel");
+    return SB_OK;
+}
+
+static int validate_grid(const sb_grid* g) {
+    if (!g) return fail(SB_ERR_INVALID_ARG, "grid is NULL");
+    if (g->reserved != 0) return fail(SB_ERR_INVALID_ARG, "grid.reserved must be 0");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(SB_ERR_SHAPE, "grid dimensions must be >= 1 (got %d x %d x %d)", g->nx, g->ny, g->nz);
+    if ((int64_t)g->nx * g->ny * g->nz > ((int64_t)1 << 31) - 1)
+        return fail(SB_ERR_SHAPE, "grid has more than 2^31 - 1 voxels");
+    if (!isfinite(g->x0) || !isfinite(g->y0) || !isfinite(g->z0) || !isfinite(g->h))
+        return fail(SB_ERR_NONFINITE, "grid origin and pitch must be finite");
+    if (!(g->h > 0.0)) return fail(SB_ERR_INVALID_ARG, "grid pitch must be > 0");
+    return SB_OK;
+}
+
+int slingbag_voxelize(const sb_config* cfg, const sb_grid* grid, int64_t n_balls, const float* balls,
+                      const float* deform, float t, float* volume, void* stream) {
+    int64_t M = 0;
+    int st = validate_model(cfg, M);
+    if (st) return st;
+    if ((st = validate_grid(grid))) return st;
+    if (n_balls < 0 || n_balls > ((int64_t)1 << 31) - 1) return fail(SB_ERR_SHAPE, "n_balls outside 0..2^31-1");
+    if (!isfinite(t)) return fail(SB_ERR_NONFINITE, "frame time must be finite");
+    if (!volume) return fail(SB_ERR_INVALID_ARG, "volume is NULL");
+    if (n_balls > 0 && !balls) return fail(SB_ERR_INVALID_ARG, "balls is NULL");
+    if (n_balls > 0 && cfg->basis != SB_BASIS_STATIC && !deform)
+        return fail(SB_ERR_INVALID_ARG, "deform is NULL for a deformed basis");
+    DeviceState* ds;
+    if ((st = device_state(&ds))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nvox = (int64_t)grid->nx * grid->ny * grid->nz;
+    hipError_t e = launch_fill(volume, nvox, 0.f, s);
+    if (e != hipSuccess) return hip_fail(e, "fill(volume)");
+    if (n_balls == 0) return SB_OK;
+    OpParams p;
+    memset(&p, 0, sizeof p);
+    p.balls = balls;
+    p.deform = deform;
+    p.flags = ds->flags;
+    p.B = n_balls;
+    p.basis = cfg->basis;
+    p.pos_mode = cfg->pos_mode;
+    p.n_terms = cfg->basis == SB_BASIS_STATIC ? 0 : cfg->n_terms;
+    p.M = (int32_t)M;
+    p.inv_delta = 1.0;           // deform_ball then returns the size in metres
+    e = launch_voxelize(p, cfg->kernel, grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, grid->h, t,
+                        volume, s);
+    if (e != hipSuccess) return hip_fail(e, "voxelize kernel");
+    return SB_OK;
+}
+
+int slingbag_map(const sb_grid* grid, const float* volume, float* map_xy, float* map_yz, float* map_xz,
+                 void* stream) {
+    int st = validate_grid(grid);
+    if (st) return st;
+    if (!volume) return fail(SB_ERR_INVALID_ARG, "volume is NULL");
+    hipError_t e = launch_map(volume, grid->nx, grid->ny, grid->nz, map_xy, map_yz, map_xz, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "map kernels");
     return SB_OK;
 }
 

@@ -163,6 +163,34 @@ def apply_order(pb: Problem, balls, deform=None):
     return nb, nd, perm
 
 
+def voxelize(pb: Problem, balls, deform, t: float, grid, out=None):
+    """Voxel grid [nz][ny][nx] of the initial pressure of one scene's balls deformed at frame
+    time t (slingbag_voxelize).  grid = (nx, ny, nz, x0, y0, z0, h), voxel (i, j, k) centred
+    at (x0 + i h, y0 + j h, z0 + k h)."""
+    nx, ny, nz = (int(v) for v in grid[:3])
+    g = binding.make_grid(nx, ny, nz, *grid[3:])
+    B = balls.shape[1]
+    M = pb.n_coef
+    if out is None:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=balls.device)
+    binding.voxelize(pb.cfg.kernel, pb.cfg.basis, pb.cfg.pos_mode, pb.cfg.n_terms, g, B,
+                     _ptr(balls, "balls", (5, B)), _ptr(deform, "deform", (5, M, B) if M else None),
+                     float(t), _ptr(out, "volume", (nz, ny, nx)), _stream())
+    return out
+
+
+def map_projections(volume):
+    """Maximum amplitude projections of a volume [nz][ny][nx] (slingbag_map):
+    (xy [ny][nx], yz [nz][ny], xz [nz][nx])."""
+    nz, ny, nx = volume.shape
+    g = binding.make_grid(nx, ny, nz, 0.0, 0.0, 0.0, 1.0)
+    xy = torch.empty((ny, nx), dtype=torch.float32, device=volume.device)
+    yz = torch.empty((nz, ny), dtype=torch.float32, device=volume.device)
+    xz = torch.empty((nz, nx), dtype=torch.float32, device=volume.device)
+    binding.map_projections(g, _ptr(volume, "volume"), _ptr(xy, "xy"), _ptr(yz, "yz"), _ptr(xz, "xz"), _stream())
+    return xy, yz, xz
+
+
 def check() -> int:
     """Synchronise the current stream and return the device flag bits (raises on errors)."""
     return binding.check(_stream())

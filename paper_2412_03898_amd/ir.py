@@ -7,8 +7,10 @@ of Sec. 3.2 (coordinates 5e-7, peak pressure 5e-4, size 5e-7, deformation
 coefficients 5e-6, in SI units) and their step decay (x0.1 every 160
 iterations).  Forward, loss and adjoint run as one captured graph per
 iteration; the Adam updates are four launches of the library's fused kernel.
+A variant fits a seeded random minibatch of frames per iteration instead of all
+of them (every frame once per epoch); the paper does not say which it uses.
 
-State (parameters, Adam moments, iteration count, loss history) is saved to
+State (parameters, Adam moments, iteration count, loss history, frame sampler) is saved to
 and restored from an .npz file (plain arrays, no pickled objects), so a run
 can stop and resume where it left off.
 
@@ -40,16 +42,61 @@ def step_decay(it: int, step_size: int = DECAY_STEP, rate: float = DECAY_RATE) -
     return rate ** (it // step_size)
 
 
+class FrameSampler:
+    """Frames used by each IR step when the step takes a minibatch of frames (the paper
+    leaves the frame schedule open): every epoch shuffles the frames with a seeded
+    generator and cuts the permutation into steps of `per_step` frames; a short last
+    step is topped up with the first frames of the same permutation, so each step's
+    frames are distinct and each epoch visits every frame."""
+
+    def __init__(self, n_frames: int, per_step: int, seed: int = 0):
+        if not 1 <= per_step <= n_frames:
+            raise ValueError(f"frames per step must be in 1..{n_frames}")
+        self.n, self.m, self.seed = int(n_frames), int(per_step), int(seed)
+        self.epoch = 0
+        self.queue: list[list[int]] = []
+
+    def _refill(self):
+        perm = [int(i) for i in np.random.default_rng((self.seed, self.epoch)).permutation(self.n)]
+        for i in range(0, self.n, self.m):
+            step = perm[i:i + self.m]
+            self.queue.append(step + perm[:self.m - len(step)])
+        self.epoch += 1
+
+    def next(self) -> np.ndarray:
+        if not self.queue:
+            self._refill()
+        return np.array(sorted(self.queue.pop(0)), dtype=np.int64)
+
+
 class IRLoop:
     """IR loop on device tensors.
 
     pb: binding.Problem; balls [5][B] and deform [5][M][B] (or None) are updated in
-    place; measured [F][S][T] holds the measured signals.
+    place; measured [F][S][T] holds the measured signals.  With frames_per_step < F
+    (single-scene problems) each step fits a minibatch of frames drawn by FrameSampler:
+    the chosen frame times and measured frames are copied into fixed buffers that the
+    captured step reads.
     """
 
     def __init__(self, pb, balls, deform, frame_t, sensors, measured, use_graph: bool = True,
                  lrs=(LR_POS, LR_R, LR_P, LR_DEF), decay_step: int = DECAY_STEP,
-                 decay_rate: float = DECAY_RATE):
+                 decay_rate: float = DECAY_RATE, frames_per_step: int | None = None, frame_seed: int = 0):
+        self.full_frame_t, self.full_measured = frame_t, measured
+        self.sampler = None
+        F = int(pb.frame_offset[-1])
+        if frames_per_step is not None and frames_per_step < F:
+            if len(pb.ball_offset) != 2:
+                raise ValueError("frame minibatches need a single-scene problem")
+            from .binding import Problem
+            c = pb.cfg
+            pb = Problem(c.kernel, c.basis, c.pos_mode, c.n_terms, c.n_sensors, c.n_samples, c.c, c.fs, c.t0,
+                         pb.ball_offset, np.array([0, frames_per_step]))
+            self.sampler = FrameSampler(F, frames_per_step, frame_seed)
+            frame_t = torch.empty(frames_per_step, dtype=frame_t.dtype, device=frame_t.device)
+            measured = torch.empty((frames_per_step,) + tuple(measured.shape[1:]), dtype=measured.dtype,
+                                   device=measured.device)
+            self.frames = None
         self.pb, self.balls, self.deform = pb, balls, deform
         self.frame_t, self.sensors, self.measured = frame_t, sensors, measured
         self.lrs = tuple(float(x) for x in lrs)
@@ -76,6 +123,11 @@ class IRLoop:
         return self.graph.loss if self.graph is not None else self.L
 
     def step(self) -> None:
+        if self.sampler is not None:
+            self.frames = self.sampler.next()
+            idx = torch.from_numpy(self.frames).to(self.frame_t.device)
+            torch.index_select(self.full_frame_t, 0, idx, out=self.frame_t)
+            torch.index_select(self.full_measured, 0, idx, out=self.measured)
         if self.graph is not None:
             self.graph.run()
         else:
@@ -107,6 +159,20 @@ class IRLoop:
             self.graph = None
 
     # ---- checkpoint
+    def full_loss(self) -> float:
+        """Loss over every frame of the problem at the current parameters (one forward)."""
+        F = self.full_measured.shape[0]
+        if self.sampler is None:
+            pb = self.pb
+        else:
+            from .binding import Problem
+            c = self.pb.cfg
+            pb = Problem(c.kernel, c.basis, c.pos_mode, c.n_terms, c.n_sensors, c.n_samples, c.c, c.fs, c.t0,
+                         self.pb.ball_offset, np.array([0, F]))
+        y = ops.forward(pb, self.balls, self.deform, self.full_frame_t, self.sensors)
+        L, _ = ops.loss(pb, y, self.full_measured)
+        return float(L.item())
+
     def state_arrays(self) -> dict:
         st = {"iteration": np.array(self.iteration, dtype=np.int64),
               "losses": np.array(self.losses, dtype=np.float64),
@@ -118,6 +184,10 @@ class IRLoop:
         for i, (m, v) in enumerate(self.moments):
             st[f"m{i}"] = m.detach().cpu().numpy()
             st[f"v{i}"] = v.detach().cpu().numpy()
+        if self.sampler is not None:
+            st["sampler"] = np.array([self.sampler.n, self.sampler.m, self.sampler.seed, self.sampler.epoch],
+                                     dtype=np.int64)
+            st["sampler_queue"] = np.array(self.sampler.queue, dtype=np.int64).reshape(-1, self.sampler.m)
         return st
 
     def save(self, path: str) -> None:
@@ -139,6 +209,12 @@ class IRLoop:
                 v.copy_(torch.from_numpy(z[f"v{i}"]))
             self.iteration = int(z["iteration"])
             self.losses = [float(x) for x in z["losses"]]
+            if self.sampler is not None:
+                n, m, seed, epoch = (int(x) for x in z["sampler"])
+                if (n, m) != (self.sampler.n, self.sampler.m):
+                    raise ValueError("checkpoint was taken with another frame minibatch size")
+                self.sampler.seed, self.sampler.epoch = seed, epoch
+                self.sampler.queue = [[int(x) for x in row] for row in z["sampler_queue"]]
         torch.cuda.synchronize()
 
 

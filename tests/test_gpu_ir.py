@@ -60,3 +60,36 @@ def test_ir_checkpoint_resume(tmp_path):
     for x, y, tol in ((c.balls, a.balls, 1e-6), (c.deform, a.deform, 1e-4)):
         x, y = x.cpu().numpy(), y.cpu().numpy()
         assert np.linalg.norm(x - y) <= tol * np.linalg.norm(y)
+
+
+def test_ir_frame_minibatch(tmp_path):
+    """Two of four frames per step: the loss over all frames falls, and a resumed run
+    draws the same frames as an uninterrupted one."""
+    from paper_2412_03898_amd import ir
+    pb, b0, d0, ft, sens, measured = _problem()
+    _say("IR frame minibatch 2 of 4, 20 iterations")
+    a = ir.IRLoop(pb, b0.clone(), d0.clone(), ft, sens, measured, frames_per_step=2, frame_seed=7)
+    L0 = a.full_loss()
+    frames = []
+    for _ in range(20):
+        a.run(1)
+        frames.append(a.frames.tolist())
+    L1 = a.full_loss()
+    a.close()
+    _say(f"full loss {L0:.4e} -> {L1:.4e}")
+    assert L1 < 0.9 * L0
+    b = ir.IRLoop(pb, b0.clone(), d0.clone(), ft, sens, measured, frames_per_step=2, frame_seed=7)
+    b.run(9)
+    path = str(tmp_path / "mb.npz")
+    b.save(path)
+    b.close()
+    c = ir.IRLoop(pb, b0.clone(), d0.clone(), ft, sens, measured, frames_per_step=2, frame_seed=7)
+    c.load(path)
+    got = []
+    for _ in range(11):
+        c.run(1)
+        got.append(c.frames.tolist())
+    c.close()
+    assert got == frames[9:]
+    x, y = c.balls.cpu().numpy(), a.balls.cpu().numpy()
+    assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(y)

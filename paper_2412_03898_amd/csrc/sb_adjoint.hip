@@ -347,7 +347,7 @@ template <int MREG, int OCC>
 __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
     static_assert(kPfxRow == 128, "two samples per lane");
     __shared__ PfxSlot slots[2][4];
-    __shared__ float s_sx[kAdjMaxSplit], s_sy[kAdjMaxSplit], s_sz[kAdjMaxSplit];
+    __shared__ double s_sx[kAdjMaxSplit], s_sy[kAdjMaxSplit], s_sz[kAdjMaxSplit];   // sensors of the split
     __shared__ int s_org[kAdjMaxSplit];
     __shared__ double s_fb[2 * SB_MAX_FOURIER];
     __shared__ float s_red[4][8];
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
             // row origins: every window of the chunk starts at or after o + 1
             for (int j = tid; j < ns; j += 256) {
                 double dmin, dmax;
-                box_distance_range(lo, hi, (double)s_sx[j], (double)s_sy[j], (double)s_sz[j], dmin, dmax);
+                box_distance_range(lo, hi, s_sx[j], s_sy[j], s_sz[j], dmin, dmax);
                 const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
                 s_org[j] = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
             }
@@ -450,9 +450,9 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                 for (int u = 0; u < nu; ++u) {
                     const int j = 4 * g + u;
                     const PfxSlot& sl = slots[buf][u];
-                    const double dx = bl.x - (double)s_sx[j];
-                    const double dy = bl.y - (double)s_sy[j];
-                    const double dz = bl.z - (double)s_sz[j];
+                    const double dx = bl.x - s_sx[j];
+                    const double dy = bl.y - s_sy[j];
+                    const double dz = bl.z - s_sz[j];
                     float inv_r;
                     const double r = dist64(dx, dy, dz, inv_r);
                     const double tau = fma(r, p.inv_delta, -p.t0fs);
@@ -509,20 +509,29 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                         }
                     }
                     if (use) {
+                        // C = P_f delta / (4 r); constant factors (P_f delta / 4, -2 rho / delta,
+                        // delta / 4) are applied once per frame below
                         const float A = fmaf(-rho * rho, Sr, (float)Sw);
                         const float Bs = (float)St;
-                        const float Cr = delta * 0.25f * inv_r;   // C / P_f
-                        const float C = bl.amp * Cr;
-                        const float dLdr = 2.f * C * Bs * inv_delta_f - C * A * inv_r;
-                        const float dLdR = -2.f * rho * C * Sr * inv_delta_f;
-                        const float dLdP = Cr * A;
-                        g5[0] = fmaf(dLdr, (float)dx * inv_r, g5[0]);
-                        g5[1] = fmaf(dLdr, (float)dy * inv_r, g5[1]);
-                        g5[2] = fmaf(dLdr, (float)dz * inv_r, g5[2]);
-                        g5[3] += dLdR;
-                        g5[4] += dLdP;
+                        const float q = (2.f * inv_delta_f) * Bs - A * inv_r;   // dL/dr / (C)
+                        const float qr = q * inv_r * inv_r;                      // times 1/r for the direction
+                        g5[0] = fmaf(qr, (float)dx, g5[0]);
+                        g5[1] = fmaf(qr, (float)dy, g5[1]);
+                        g5[2] = fmaf(qr, (float)dz, g5[2]);
+                        g5[3] = fmaf(inv_r, Sr, g5[3]);
+                        g5[4] = fmaf(inv_r, A, g5[4]);
                     }
                 }
+            }
+            // per-frame factors of the accumulated sums: dL/dx_f = (P_f delta/4) sum q dx/r^2,
+            // dL/dR_f = -(2 rho/delta)(P_f delta/4) sum Sr/r, dL/dP_f = (delta/4) sum A/r
+            {
+                const float cp = live ? bl.amp * delta * 0.25f : 0.f;
+                g5[0] *= cp;
+                g5[1] *= cp;
+                g5[2] *= cp;
+                g5[3] *= -2.f * rho * inv_delta_f * cp;
+                g5[4] *= delta * 0.25f;
             }
             // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame
             if (live) {

@@ -544,7 +544,7 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
     best = 3.0e38f;
     int best_occ = g_tune.adj_occ, best_items = g_tune.adj_items;
     for (int occ : {2, 3, 4}) {
-        for (int items : {2048, 4096, 8192}) {
+        for (int items : {2048, 4096, 8192, 16384}) {
             if (cfg->kernel != SB_KERNEL_UNIFORM && occ != 2) continue;
             g_tune.adj_occ = occ;
             g_tune.adj_items = items;

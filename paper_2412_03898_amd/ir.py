@@ -236,7 +236,8 @@ def _per_frame_static(wl, balls_np, deform_np):
 
 def large_ir(iters: int = 200, per_frame_iters: int = 3, tuning=None, n_balls: int = 1_000_000,
              n_frames: int = 32, n_sensors: int = 2048, checkpoint: str | None = None,
-             resume: str | None = None, log=print) -> dict:
+             resume: str | None = None, log=print, frames_per_step: int | None = None,
+             decay_step: int = DECAY_STEP) -> dict:
     """The large 4D IR run (see module docstring); returns the result record."""
     from . import binding, synth, tune
 
@@ -265,7 +266,7 @@ def large_ir(iters: int = 200, per_frame_iters: int = 3, tuning=None, n_balls: i
 
     torch.cuda.reset_peak_memory_stats()
     free0, total = torch.cuda.mem_get_info()
-    loop = IRLoop(pb, balls, deform, ft, sens, measured)
+    loop = IRLoop(pb, balls, deform, ft, sens, measured, frames_per_step=frames_per_step, decay_step=decay_step)
     if resume:
         loop.load(resume)
         log(f"[ir] resumed at iteration {loop.iteration}")
@@ -289,14 +290,17 @@ def large_ir(iters: int = 200, per_frame_iters: int = 3, tuning=None, n_balls: i
     if checkpoint:
         loop.save(checkpoint)
     losses = list(loop.losses)
+    full_loss = loop.full_loss() if loop.sampler is not None else None
     loop.close()
     # steady-state ms/iteration: skip the first iteration (graph warm-up)
     steady = (times[-1] - times[0]) / (len(times) - 1) * 1e3 if len(times) > 1 else elapsed * 1e3
-    pairs = pb.pairs()
+    pairs = pb.pairs() * (frames_per_step or wl.n_frames) // wl.n_frames
     rec = {"workload": wl.name, "balls": wl.n_balls, "frames": wl.n_frames, "sensors": wl.n_sensors,
            "samples": wl.n_samples, "iterations": loop.iteration, "tuning": choice,
            "ms_per_iter": round(steady, 2), "gpairs_per_s": round(pairs / (steady * 1e-3) / 1e9, 3),
+           "frames_per_step": frames_per_step or wl.n_frames, "decay_step": decay_step,
            "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
+           "loss_all_frames_end": full_loss,
            "loss_curve": [losses[i] for i in range(0, len(losses), 10)],
            "peak_mem_mb_torch": round(peak_torch / 2**20, 1),
            "peak_mem_mb_device": round((total - min_free[0]) / 2**20, 1),
@@ -365,10 +369,14 @@ def main():
     ap.add_argument("--tuning", default=None, help="COLUMN,OCCUPANCY,ITEMS instead of autotuning")
     ap.add_argument("--checkpoint", default=None, help="save the state here at the end (.npz)")
     ap.add_argument("--resume", default=None, help="continue from a saved state (.npz)")
+    ap.add_argument("--frames-per-step", type=int, default=None,
+                    help="fit a random minibatch of this many frames per iteration (default: all)")
+    ap.add_argument("--decay-step", type=int, default=DECAY_STEP, help="iterations per x0.1 learning-rate step")
     args = ap.parse_args()
     tuning = [int(x) for x in args.tuning.split(",")] if args.tuning else None
     rec = large_ir(args.iters, args.per_frame_iters, tuning, args.balls, args.frames, args.sensors,
-                   args.checkpoint, args.resume, log=lambda s: print(s, flush=True))
+                   args.checkpoint, args.resume, log=lambda s: print(s, flush=True),
+                   frames_per_step=args.frames_per_step, decay_step=args.decay_step)
     print(json.dumps(rec), flush=True)
 
 

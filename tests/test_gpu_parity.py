@@ -345,7 +345,7 @@ def test_autotune_then_parity():
     saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
     try:
         choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
-        assert choice[0] in (64, 128) and choice[1] in (2, 3, 4) and choice[2] in (2048, 4096, 8192)
+        assert choice[0] in (64, 128) and choice[1] in (2, 3, 4) and choice[2] in (2048, 4096, 8192, 16384)
         y = ops.forward(pb, balls, deform, ft, sens)
         ops.check()
         ref = oracle.forward(wl)

@@ -34,6 +34,8 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # 39.32 T lane-ops/s
 
 # Learning rates of Sec. 3.2 (coordinates, peak pressure, size, deformation).
 LR_POS, LR_P, LR_R, LR_DEF = 5e-7, 5e-4, 5e-7, 5e-6
+# projection of the updates (as in the IR loop): peak pressure >= 0, size >= 1 um
+LO = {"pos": -float("inf"), "R": 1e-6, "P": 0.0, "def": -float("inf")}
 
 
 def workloads():
@@ -134,8 +136,9 @@ def ir_4d_comparison(steps, warmup):
     L = torch.empty((), dtype=torch.float64, device="cuda")
     gb = torch.empty_like(balls)
     gd = torch.empty_like(deform)
-    groups = [(balls[0:3], gb[0:3], LR_POS), (balls[3], gb[3], LR_R), (balls[4], gb[4], LR_P), (deform, gd, LR_DEF)]
-    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in groups]
+    groups = [(balls[0:3], gb[0:3], LR_POS, LO["pos"]), (balls[3], gb[3], LR_R, LO["R"]),
+              (balls[4], gb[4], LR_P, LO["P"]), (deform, gd, LR_DEF, LO["def"])]
+    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _, _ in groups]
     it = [0]
 
     def batched():
@@ -143,8 +146,8 @@ def ir_4d_comparison(steps, warmup):
         ops.loss(pb, y, d, residual=r, loss_out=L)
         ops.adjoint(pb, balls, deform, ft, sens, r, grad_balls=gb, grad_deform=gd)
         it[0] += 1
-        for (p, g, lr), (m, v) in zip(groups, state):
-            ops.adam_(p, g, m, v, lr, it[0])
+        for (p, g, lr, lo), (m, v) in zip(groups, state):
+            ops.adam_(p, g, m, v, lr, it[0], lo=lo)
 
     ms_batched = run(batched)
     mem_batched = torch.cuda.max_memory_allocated() / 2**20
@@ -174,9 +177,9 @@ def ir_4d_comparison(steps, warmup):
             ops.loss(pf, fy, d[f:f + 1], residual=fr, loss_out=fL)
             ops.adjoint(pf, fb[f], None, t0, sens, fr, grad_balls=fg[f])
             x, g = fb[f], fg[f]
-            for (p, gg, lr), (m, v) in zip(((x[0:3], g[0:3], LR_POS), (x[3], g[3], LR_R), (x[4], g[4], LR_P)),
-                                           fstate[f]):
-                ops.adam_(p, gg, m, v, lr, fit[0])
+            for (p, gg, lr, lo), (m, v) in zip(((x[0:3], g[0:3], LR_POS, LO["pos"]), (x[3], g[3], LR_R, LO["R"]),
+                                                (x[4], g[4], LR_P, LO["P"])), fstate[f]):
+                ops.adam_(p, gg, m, v, lr, fit[0], lo=lo)
 
     ms_frames = run(per_frame)
     mem_frames = torch.cuda.max_memory_allocated() / 2**20
@@ -208,8 +211,9 @@ def uneven_batch_timing(steps, warmup):
     y, r = torch.empty_like(d), torch.empty_like(d)
     L = torch.empty((), dtype=torch.float64, device="cuda")
     gb, gd = torch.empty_like(balls), torch.empty_like(deform)
-    groups = [(balls[0:3], gb[0:3], LR_POS), (balls[3], gb[3], LR_R), (balls[4], gb[4], LR_P), (deform, gd, LR_DEF)]
-    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in groups]
+    groups = [(balls[0:3], gb[0:3], LR_POS, LO["pos"]), (balls[3], gb[3], LR_R, LO["R"]),
+              (balls[4], gb[4], LR_P, LO["P"]), (deform, gd, LR_DEF, LO["def"])]
+    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _, _ in groups]
     it = [0]
 
     def step():
@@ -217,8 +221,8 @@ def uneven_batch_timing(steps, warmup):
         ops.loss(pb, y, d, residual=r, loss_out=L)
         ops.adjoint(pb, balls, deform, ft, sens, r, grad_balls=gb, grad_deform=gd)
         it[0] += 1
-        for (p, g, lr), (m, v) in zip(groups, state):
-            ops.adam_(p, g, m, v, lr, it[0])
+        for (p, g, lr, lo), (m, v) in zip(groups, state):
+            ops.adam_(p, g, m, v, lr, it[0], lo=lo)
 
     for _ in range(warmup):
         step()
@@ -333,10 +337,11 @@ def main():
     L = torch.empty((), dtype=torch.float64, device="cuda")
     gb = torch.empty_like(balls)
     gd = torch.empty_like(deform) if deform is not None else None
-    groups = [(balls[0:3], gb[0:3], LR_POS), (balls[3], gb[3], LR_R), (balls[4], gb[4], LR_P)]
+    groups = [(balls[0:3], gb[0:3], LR_POS, LO["pos"]), (balls[3], gb[3], LR_R, LO["R"]),
+              (balls[4], gb[4], LR_P, LO["P"])]
     if deform is not None:
-        groups.append((deform, gd, LR_DEF))
-    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in groups]
+        groups.append((deform, gd, LR_DEF, LO["def"]))
+    state = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _, _ in groups]
     step_no = [0]
 
     def step():
@@ -344,8 +349,8 @@ def main():
         ops.loss(pb, y, d, residual=r, loss_out=L)
         ops.adjoint(pb, balls, deform, ft, sens, r, grad_balls=gb, grad_deform=gd)
         step_no[0] += 1
-        for (p, g, lr), (m, v) in zip(groups, state):
-            ops.adam_(p, g, m, v, lr, step_no[0])
+        for (p, g, lr, lo), (m, v) in zip(groups, state):
+            ops.adam_(p, g, m, v, lr, step_no[0], lo=lo)
 
     for _ in range(args.warmup):
         step()
@@ -367,16 +372,16 @@ def main():
     ms_graph = None
     graph = None if args.no_graph else ops.StepGraph(pb, balls, deform, ft, sens, d)
     if graph is not None:
-        ggroups = [(balls[0:3], graph.grad_balls[0:3], LR_POS), (balls[3], graph.grad_balls[3], LR_R),
-                   (balls[4], graph.grad_balls[4], LR_P)]
+        ggroups = [(balls[0:3], graph.grad_balls[0:3], LR_POS, LO["pos"]),
+                   (balls[3], graph.grad_balls[3], LR_R, LO["R"]), (balls[4], graph.grad_balls[4], LR_P, LO["P"])]
         if deform is not None:
-            ggroups.append((deform, graph.grad_deform, LR_DEF))
+            ggroups.append((deform, graph.grad_deform, LR_DEF, LO["def"]))
 
         def gstep():
             graph.run()
             step_no[0] += 1
-            for (p, g, lr), (m, v) in zip(ggroups, state):
-                ops.adam_(p, g, m, v, lr, step_no[0])
+            for (p, g, lr, lo), (m, v) in zip(ggroups, state):
+                ops.adam_(p, g, m, v, lr, step_no[0], lo=lo)
 
         for _ in range(args.warmup):
             gstep()

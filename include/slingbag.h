@@ -167,13 +167,16 @@ int slingbag_permute(const float* src, float* dst, int64_t rows, int64_t n, cons
 /* One Adam step of the iterative reconstruction (Sec. 3.2 updates each
  * parameter group - coordinates, peak pressure, size, deformation
  * coefficients - with its own learning rate; the optimiser is not named, Adam
- * is used).  For i < n, with g = grad[i] and t = step >= 1:
+ * is used), followed by a projection onto [lo, hi].  For i < n, with
+ * g = grad[i] and t = step >= 1:
  *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
- *   param -= lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ *   param = clamp(param - lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps), lo, hi).
  * param, m, v are updated in place (DEVICE, n floats each).  Call once per
- * parameter group.  0 <= beta < 1, eps > 0. */
+ * parameter group.  0 <= beta < 1, eps > 0, lo <= hi (use -INFINITY / INFINITY
+ * for no bound; an IR loop keeps peak pressure >= 0 and size > 0 this way). */
 int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n,
-                  float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+                  float lr, float beta1, float beta2, float eps, int32_t step, float lo, float hi,
+                  void* stream);
 
 /* Waits for `stream`, returns the device flag bits raised since the last
  * check in *flags (HOST, may be NULL) and clears them.  Returns

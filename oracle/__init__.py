@@ -187,16 +187,17 @@ def deformed(wl, frame: int, balls=None, deform=None) -> np.ndarray:
     return out
 
 
-def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, lo=-np.inf, hi=np.inf):
     """One bias-corrected Adam step in float64 (new param, m, v): the textbook update
-    m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, p -= lr mhat / (sqrt(vhat) + eps)."""
+    m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, p -= lr mhat / (sqrt(vhat) + eps),
+    then the projection of p onto [lo, hi]."""
     p = np.asarray(param, dtype=np.float64)
     g = np.asarray(grad, dtype=np.float64)
     m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
     v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
     mhat = m / (1.0 - beta1 ** step)
     vhat = v / (1.0 - beta2 ** step)
-    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+    return np.clip(p - lr * mhat / (np.sqrt(vhat) + eps), lo, hi), m, v
 
 
 def voxelize(kernel: int, attrs, grid, gauss_window: float = 10.0, n_threads: int = 0) -> np.ndarray:

@@ -66,7 +66,7 @@ _SIGS = {
                          _VP, _VP, _VP],
     "slingbag_check": [_VP, ctypes.POINTER(ctypes.c_uint32)],
     "slingbag_adam": [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
-                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, _VP],
+                      ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _VP],
     "slingbag_order": [ctypes.POINTER(Batch), _VP, _VP, _VP],
     "slingbag_permute": [_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, _VP],
     "slingbag_plan_create": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP, _VP,
@@ -180,8 +180,8 @@ def adjoint(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, re
 
 
 def adam(param: int, grad: int, m: int, v: int, n: int, lr: float, beta1: float, beta2: float,
-         eps: float, step: int, stream: int = 0):
-    _check(load().slingbag_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, stream))
+         eps: float, step: int, stream: int = 0, lo: float = -float("inf"), hi: float = float("inf")):
+    _check(load().slingbag_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, lo, hi, stream))
 
 
 def plan_create(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, measured: int,

@@ -370,15 +370,16 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* b
 }
 
 int slingbag_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
-                  float beta1, float beta2, float eps, int32_t step, void* stream) {
+                  float beta1, float beta2, float eps, int32_t step, float lo, float hi, void* stream) {
     if (n < 0) return fail(SB_ERR_SHAPE, "n must be >= 0");
     if (n > 0 && (!param || !grad || !m || !v)) return fail(SB_ERR_INVALID_ARG, "NULL Adam buffer");
     if (step < 1) return fail(SB_ERR_INVALID_ARG, "step must be >= 1 (got %d)", step);
     if (!isfinite(lr) || !isfinite(eps) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
         !(eps > 0.f))
         return fail(SB_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+    if (isnan(lo) || isnan(hi) || !(lo <= hi)) return fail(SB_ERR_INVALID_ARG, "Adam bounds need lo <= hi");
     time_mark(kTimeAdam, 0, (hipStream_t)stream);
-    hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    hipError_t e = launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, step, lo, hi, (hipStream_t)stream);
     time_mark(kTimeAdam, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adam kernel");
     return SB_OK;

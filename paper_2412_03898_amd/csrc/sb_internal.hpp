@@ -342,6 +342,6 @@ hipError_t launch_voxelize(const OpParams& p, int kernel, int nx, int ny, int nz
                            double z0, double h, float t, float* vol, hipStream_t st);
 hipError_t launch_map(const float* vol, int nx, int ny, int nz, float* xy, float* yz, float* xz, hipStream_t st);
 hipError_t launch_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
-                       float b1, float b2, float eps, int step, hipStream_t st);
+                       float b1, float b2, float eps, int step, float lo, float hi, hipStream_t st);
 
 }  // namespace sb

@@ -106,7 +106,7 @@ namespace sb {
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ param, const float* __restrict__ grad,
                                                    float* __restrict__ m, float* __restrict__ v, int64_t n,
                                                    float lr, float b1, float b2, float eps, float c1,
-                                                   float c2) {
+                                                   float c2, float lo, float hi) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const float g = grad[i];
@@ -114,19 +114,20 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ param, co
         const float vi = b2 * v[i] + (1.f - b2) * g * g;
         m[i] = mi;
         v[i] = vi;
-        param[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        const float p = param[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        param[i] = fminf(fmaxf(p, lo), hi);      // projection onto [lo, hi]
     }
 }
 
 hipError_t launch_adam(float* param, const float* grad, float* m, float* v, int64_t n, float lr,
-                       float b1, float b2, float eps, int step, hipStream_t st) {
+                       float b1, float b2, float eps, int step, float lo, float hi, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const float c1 = (float)(1.0 / (1.0 - pow((double)b1, (double)step)));
     const float c2 = (float)(1.0 / (1.0 - pow((double)b2, (double)step)));
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, st, param, grad, m, v, n, lr,
-                       b1, b2, eps, c1, c2);
+                       b1, b2, eps, c1, c2, lo, hi);
     return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ from . import ops
 # Sec. 3.2: initial learning rates and step decay
 LR_POS, LR_P, LR_R, LR_DEF = 5e-7, 5e-4, 5e-7, 5e-6
 DECAY_STEP, DECAY_RATE = 160, 0.1
+# every update is projected back into the model's domain: peak pressure >= 0, size >= R_MIN
+R_MIN = 1e-6
 
 
 def step_decay(it: int, step_size: int = DECAY_STEP, rate: float = DECAY_RATE) -> float:
@@ -112,11 +114,12 @@ class IRLoop:
             self.gd = torch.empty_like(deform) if deform is not None else None
         gb = self.graph.grad_balls if self.graph is not None else self.gb
         gd = self.graph.grad_deform if self.graph is not None else self.gd
-        self.groups = [(balls[0:3], gb[0:3], self.lrs[0]), (balls[3], gb[3], self.lrs[1]),
-                       (balls[4], gb[4], self.lrs[2])]
+        inf = float("inf")
+        self.groups = [(balls[0:3], gb[0:3], self.lrs[0], -inf), (balls[3], gb[3], self.lrs[1], R_MIN),
+                       (balls[4], gb[4], self.lrs[2], 0.0)]
         if deform is not None:
-            self.groups.append((deform, gd, self.lrs[3]))
-        self.moments = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _ in self.groups]
+            self.groups.append((deform, gd, self.lrs[3], -inf))
+        self.moments = [(torch.zeros_like(p), torch.zeros_like(p)) for p, _, _, _ in self.groups]
 
     # ---- one iteration
     def _loss_tensor(self):
@@ -137,8 +140,8 @@ class IRLoop:
                         grad_balls=self.gb, grad_deform=self.gd)
         factor = step_decay(self.iteration, self.decay_step, self.decay_rate)
         t = self.iteration + 1
-        for (p, g, lr), (m, v) in zip(self.groups, self.moments):
-            ops.adam_(p, g, m, v, lr * factor, t)
+        for (p, g, lr, lo), (m, v) in zip(self.groups, self.moments):
+            ops.adam_(p, g, m, v, lr * factor, t, lo=lo)
         self.iteration += 1
 
     def run(self, n: int, on_iter=None) -> list[float]:
@@ -339,9 +342,9 @@ def _per_frame_path(wl, pb, balls, ft, sens, measured, iters, log) -> dict:
             ops.loss(pf, fy, measured[f:f + 1], residual=fr, loss_out=fL)
             ops.adjoint(pf, fb[f], None, t0, sens, fr, grad_balls=fg[f])
             x, g = fb[f], fg[f]
-            for (p, gg, lr), (m, v) in zip(((x[0:3], g[0:3], LR_POS), (x[3], g[3], LR_R), (x[4], g[4], LR_P)),
-                                           fstate[f]):
-                ops.adam_(p, gg, m, v, lr, it + 1)
+            for (p, gg, lr, lo), (m, v) in zip(((x[0:3], g[0:3], LR_POS, -float("inf")), (x[3], g[3], LR_R, R_MIN),
+                                                (x[4], g[4], LR_P, 0.0)), fstate[f]):
+                ops.adam_(p, gg, m, v, lr, it + 1, lo=lo)
 
     one(0)
     torch.cuda.synchronize()

@@ -79,14 +79,15 @@ def adjoint(pb: Problem, balls, deform, frame_t, sensors, residual, grad_balls=N
     return grad_balls, (grad_deform if M else None)
 
 
-def adam_(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
-    """In-place Adam step on one parameter group (slingbag_adam); tensors of equal size."""
+def adam_(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, lo=-float("inf"), hi=float("inf")):
+    """In-place Adam step on one parameter group, projected onto [lo, hi] (slingbag_adam);
+    tensors of equal size."""
     n = param.numel()
     for t, name in ((grad, "grad"), (m, "m"), (v, "v")):
         if t.numel() != n:
             raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
     binding.adam(_ptr(param, "param"), _ptr(grad, "grad"), _ptr(m, "m"), _ptr(v, "v"), n,
-                 float(lr), float(beta1), float(beta2), float(eps), int(step), _stream())
+                 float(lr), float(beta1), float(beta2), float(eps), int(step), _stream(), float(lo), float(hi))
     return param
 
 

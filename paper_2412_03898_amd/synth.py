@@ -357,6 +357,65 @@ def workload_large_ir(n_balls: int = 1_000_000, n_frames: int = 32, n_sensors: i
                          F=n_frames, basis=1, K=K, extra={"half": half, "shell": shell})
 
 
+def heart_phantom(n_sensors: int = 1024, n_frames: int = 17, spacing: float = 0.5e-3,
+                  slab_half: float = 12e-3, slab_thick: float = 1e-3, axes=(6e-3, 4.5e-3, 3.5e-3),
+                  size_amp: float = 0.25, p_amp: float = 0.4, seed: int = 30):
+    """Pulsating-heart phantom in the manner of Sec. 3.1 (its dimensions are not given).
+
+    Three mutually perpendicular slabs (|z|, |x|, |y| <= slab_thick, the other two
+    coordinates within +-slab_half) of uniform pressure, filled with uniform spheres of
+    radius 0.6 spacing on a regular grid, static; and a central Gaussian ellipsoid
+    (semi-axes `axes`) made of Gaussian balls (std 0.6 spacing) on the same grid out to
+    1.5 semi-axes, pressure exp(-q^2/2) at normalised radius q, pulsating over the
+    frames: positions (about the centre) and sizes scale by 1 + size_amp sin(2 pi t),
+    pressure by 1 + p_amp sin(2 pi t) (Eq. 1, multiplicative, one Fourier harmonic).
+    1,024 sensors on the full 60 mm Fibonacci sphere, 17 frames, cube +-25.6 mm.
+
+    Returns (slabs, ellipsoid): two single-scene workloads sharing sensors, frames and
+    record window (uniform-sphere and Gaussian-ball kernels); the measured signals are
+    the sum of their forwards.
+    """
+    rng = np.random.default_rng(seed)
+    half_cube, shell = 25.6e-3, 0.060
+    g = np.arange(-slab_half, slab_half + 1e-9, spacing)
+    t = np.arange(-slab_thick, slab_thick + 1e-9, spacing)
+    slabs = []
+    for axis in range(3):                       # thin along axis
+        A, Bg, Cg = np.meshgrid(t, g, g, indexing="ij")
+        pts = np.zeros((3, A.size))
+        pts[axis] = A.ravel()
+        pts[(axis + 1) % 3] = Bg.ravel()
+        pts[(axis + 2) % 3] = Cg.ravel()
+        slabs.append(pts)
+    sp = np.concatenate(slabs, axis=1)
+    sp += rng.normal(0.0, 0.02 * spacing, size=sp.shape)      # break exact lattice ties
+    n_s = sp.shape[1]
+    slab_balls = np.vstack([sp, np.full((1, n_s), 0.6 * spacing), np.full((1, n_s), 0.5)])
+    ax = np.asarray(axes)
+    r = np.arange(-1.5 * ax.max(), 1.5 * ax.max() + 1e-9, spacing)
+    X, Y, Z = np.meshgrid(r, r, r, indexing="ij")
+    q2 = (X / ax[0]) ** 2 + (Y / ax[1]) ** 2 + (Z / ax[2]) ** 2
+    keep = q2 <= 1.5 ** 2
+    ep = np.stack([X[keep], Y[keep], Z[keep]])
+    n_e = ep.shape[1]
+    ell_balls = np.vstack([ep, np.full((1, n_e), 0.6 * spacing), np.exp(-0.5 * q2[keep])[None]])
+    D = np.zeros((5, 2, n_e))
+    D[0:4, 1] = size_amp                         # sin(2 pi t) coefficient: x, y, z, R
+    D[4, 1] = p_amp                              # and P
+    sensors = fibonacci_sphere(n_sensors, shell, hemisphere=False)
+    r_max = 1.1 * 6 * 0.6 * spacing * (1 + size_amp)
+    k0 = record_start(shell, half_cube, r_max, 0.0)
+    T = record_length_needed(shell, half_cube, r_max, 0.0, k0)
+    T = int(math.ceil(T / 64.0) * 64)
+    extra = {"half": half_cube, "shell": shell, "spacing": spacing}
+    slabs_wl = _single_scene("heart-slabs", np.ascontiguousarray(slab_balls.astype(np.float32)), sensors, T, k0,
+                             F=n_frames, kernel=0, extra=extra)
+    ell_wl = _single_scene("heart-ellipsoid", np.ascontiguousarray(ell_balls.astype(np.float32)), sensors, T, k0,
+                           deform=np.ascontiguousarray(D.astype(np.float32)), F=n_frames, basis=1, K=1,
+                           pos_mode=1, kernel=1, extra=extra)
+    return slabs_wl, ell_wl
+
+
 def synthetic_residual(n_frames: int, n_sensors: int, n_samples: int, seed: int) -> np.ndarray:
     """Seeded N(0, 1e-3) residual [F][S][T] for adjoint-only checks."""
     rng = np.random.default_rng(seed)

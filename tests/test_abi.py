@@ -144,5 +144,12 @@ def test_order_and_permute_validation():
     assert lib.slingbag_order(ctypes.byref(b), None, None, None) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_permute(None, None, 1, 4, None, None) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_permute(None, None, -1, 4, None, None) == binding.SB_ERR_SHAPE
-    assert lib.slingbag_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) \
+    inf = float("inf")
+    assert lib.slingbag_adam(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, -inf, inf, None) \
         == binding.SB_ERR_INVALID_ARG
+    # bounds must satisfy lo <= hi (checked before any device work: n = 0 here)
+    assert lib.slingbag_adam(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, 1.0, 0.0, None) \
+        == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_adam(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, float("nan"), inf, None) \
+        == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_adam(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, 0.0, inf, None) == binding.SB_OK

@@ -28,5 +28,6 @@ def test_adam_matches_oracle(lo, hi):
     # FP32 state: each step moves p by at most lr (about); allow FP32 rounding of that
     assert np.max(np.abs(got - ref_p)) <= 1e-6 + 1e-5 * lr * 5
     assert np.all(got >= lo) and np.all(got <= hi)
-    np.testing.assert_allclose(mt.cpu().numpy(), ref_m, rtol=1e-5, atol=1e-9)
-    np.testing.assert_allclose(vt.cpu().numpy(), ref_v, rtol=1e-5, atol=1e-12)
+    # moments in FP32: rounding relative to their magnitude (m cancels to ~0 for some entries)
+    np.testing.assert_allclose(mt.cpu().numpy(), ref_m, rtol=1e-5, atol=1e-6 * np.abs(ref_m).max())
+    np.testing.assert_allclose(vt.cpu().numpy(), ref_v, rtol=1e-5, atol=1e-6 * np.abs(ref_v).max())

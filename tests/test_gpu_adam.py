@@ -23,7 +23,10 @@ def test_adam_matches_oracle(lo, hi):
     for step in range(1, 6):
         g = rng.normal(0.0, 1.0, n).astype(np.float32) * (10.0 ** rng.uniform(-3, 1, n)).astype(np.float32)
         ops.adam_(pt, torch.from_numpy(g).cuda(), mt, vt, lr, step, lo=lo, hi=hi)
-        ref_p, ref_m, ref_v = oracle.adam_step(ref_p, g, ref_m, ref_v, lr, step, lo=lo, hi=hi)
+        # the C ABI takes the hyper-parameters in FP32: the oracle gets the same values
+        ref_p, ref_m, ref_v = oracle.adam_step(ref_p, g, ref_m, ref_v, float(np.float32(lr)), step,
+                                               beta1=float(np.float32(0.9)), beta2=float(np.float32(0.999)),
+                                               eps=float(np.float32(1e-8)), lo=lo, hi=hi)
     got = pt.cpu().numpy().astype(np.float64)
     # FP32 state: each step moves p by at most lr (about); allow FP32 rounding of that
     assert np.max(np.abs(got - ref_p)) <= 1e-6 + 1e-5 * lr * 5

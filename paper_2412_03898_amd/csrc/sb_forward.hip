@@ -107,6 +107,56 @@ __device__ inline void add_window(float* c, int W, float x0, float rho, float C)
     }
 }
 
+// Second-difference form of the uniform sphere's window.  The column holds, in
+// integer units of 1/s, the second difference D_k = u_k - 2 u_{k-1} + u_{k-2} of
+// the quantised trace u; the flush recovers u by two running sums.  A window's
+// trace is a ramp between three end samples (see add_window), so its second
+// difference is zero except at rows 0, 1, 2 and W-2 .. W+1: seven updates per
+// window whatever its length.  The ramp is quantised as A + B (j - 1) with integer
+// A and B, so every window's second differences sum back to exactly zero past
+// its end: all arithmetic is modulo 2^32 and the running sums return the exact
+// integer column as long as its true value fits in int32, which the caller's
+// choice of s guarantees.  Windows with W < 5 take four clamped samples (rows
+// 0 .. 5).  Rows: W + 2 for W >= 5, else 6.
+__device__ inline void add_window_d2(uint32_t* c, int W, float x0, float rho, float Cs) {
+    const float rr = rho * rho;
+    auto sq = [&](float x) {
+        const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
+        return q * q;
+    };
+    auto qn = [](float v) { return (uint32_t)__float2int_rn(v); };
+    if (W >= 5) {
+        const float xa = x0 - (float)(W - 2);             // boundary W-2 (exact in FP32)
+        const float qa = sq(xa), qb = sq(xa - 1.f);
+        const uint32_t u0 = qn(Cs * (rr - sq(x0 - 1.f)));
+        const uint32_t a = qn(Cs * fmaf(2.f, x0, -3.f));   // sample 1 of the ramp C (2 x_j - 1)
+        const uint32_t b = qn(-2.f * Cs);                  // ramp step
+        const uint32_t e1 = qn(Cs * (qa - qb)), e2 = qn(Cs * (qb - rr));
+        const uint32_t last = a + b * (uint32_t)(W - 4);   // ramp sample W-3
+        uint32_t* const p1 = c + (W - 2) * 64;
+        const uint32_t o0 = c[0], o1 = c[64], o2 = c[128];
+        const uint32_t o3 = p1[0], o4 = p1[64], o5 = p1[128], o6 = p1[192];
+        c[0] = o0 + u0;
+        c[64] = o1 + a - 2u * u0;
+        c[128] = o2 + b - a + u0;
+        p1[0] = o3 + e1 - last - b;
+        p1[64] = o4 + e2 - 2u * e1 + last;
+        p1[128] = o5 + e1 - 2u * e2;
+        p1[192] = o6 + e2;
+    } else {
+        const float q1 = sq(x0 - 1.f), q2 = sq(x0 - 2.f), q3 = sq(x0 - 3.f), q4 = sq(x0 - 4.f);
+        const uint32_t u0 = qn(Cs * (rr - q1)), u1 = qn(Cs * (q1 - q2));
+        const uint32_t u2 = qn(Cs * (q2 - q3)), u3 = qn(Cs * (q3 - q4));
+        const uint32_t o0 = c[0], o1 = c[64], o2 = c[128], o3 = c[192], o4 = c[256], o5 = c[320];
+        c[0] = o0 + u0;
+        c[64] = o1 + u1 - 2u * u0;
+        c[128] = o2 + u2 - 2u * u1 + u0;
+        c[192] = o3 + u3 - 2u * u2 + u1;
+        c[256] = o4 + u2 - 2u * u3;
+        c[320] = o5 + u3;
+    }
+}
+
 // Per-pair quantities of one ball for the wave's 64 sensors (one per lane).
 struct FwdPair {
     float Cg, xg;    // amplitude and boundary 0
@@ -151,6 +201,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
     static_assert(G == 64 * NW, "one ball per thread when staging");
     __shared__ BallF sball[G];
     __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
+    __shared__ float s_box[NW][8];                    // per wave: centre box of the chunk's tile balls, amplitude sum
     __shared__ float tile[NW][(UCAP + 1) * 64];     // per wave: a pad row, then UCAP rows of 64 sensors
 
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
@@ -185,6 +236,30 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 bl.amp = 0.f;
             }
             sball[tid] = bl;
+            if (KERNEL == SB_KERNEL_UNIFORM) {
+                // bound of the chunk's contribution to any sample: |v| <= |P delta/4| (2 rho + 1) / r
+                // for every tile window, with r at least the distance from the sensor to the
+                // box of the centres
+                // (tile windows: W + 2 <= UCAP rows with W = floor(2 rho) + 2, as in the pair set-up)
+                const bool in_tile = tid < nb && bl.rho >= 0.0 && (int)(2.0 * fmin(bl.rho, 1.0e6)) + 4 <= UCAP;
+                const float inf = __builtin_huge_valf();
+                const float lo[3] = {in_tile ? (float)bl.x : inf, in_tile ? (float)bl.y : inf,
+                                     in_tile ? (float)bl.z : inf};
+                const float hi[3] = {in_tile ? (float)bl.x : -inf, in_tile ? (float)bl.y : -inf,
+                                     in_tile ? (float)bl.z : -inf};
+                const float sa = in_tile ? fabsf(bl.amp) * fmaf(2.f, bl.rhof, 1.f) : 0.f;
+                float red[7];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    red[a] = wave_min_all(lo[a]);
+                    red[3 + a] = wave_max_all(hi[a]);
+                }
+                red[6] = wave_reduce_dpp(sa, [](float x, float y) { return x + y; });
+                if (lane == 0) {
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) s_box[wid][a] = red[a];
+                }
+            }
         }
         __syncthreads();
 
@@ -194,6 +269,46 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
         const int64_t row_off = ((int64_t)gf * p.S + (active ? s : 0)) * p.T;   // this lane's trace row
         float* out_row = p.signals + row_off;
+
+        // Uniform sphere: the tile holds second differences in units of 1/qs (add_window_d2)
+        // when a per-lane scale qs keeps every column within int32; qs = 2^30 r_min / sum,
+        // with r_min the distance from the sensor to the box of the tile balls' centres.
+        // A wave whose sensors come within a quarter of the box's far distance (the bound
+        // would cost precision) keeps the FP32 tile for this chunk.
+        float qs = 1.f, qeps = 1.f;
+        bool qmode = false;
+        if (KERNEL == SB_KERNEL_UNIFORM) {
+            float lo[3], hi[3], sum = 0.f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = s_box[0][a];
+                hi[a] = s_box[0][3 + a];
+            }
+            sum = s_box[0][6];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], s_box[w][a]);
+                    hi[a] = fmaxf(hi[a], s_box[w][3 + a]);
+                }
+                sum += s_box[w][6];
+            }
+            bool ok = true;
+            if (active) {
+                if (!(sum < __builtin_huge_valf())) {
+                    ok = false;                          // a non-finite amplitude in the chunk
+                } else if (sum > 0.f && lo[0] <= hi[0]) {
+                    double dmin, dmax;
+                    box_distance_range(lo, hi, sx, sy, sz, dmin, dmax);
+                    qs = (float)(1073741824.0 * dmin / (double)sum);
+                    ok = dmin > 0.25 * dmax && qs > 0.f && qs < __builtin_huge_valf();
+                    qeps = 1.f / qs;
+                }                                        // else: every tile amplitude is zero
+            }
+            qmode = __all(ok);
+        }
+        uint32_t* const twu = reinterpret_cast<uint32_t*>(tw);
 
         // Each lane's column covers samples o .. o + UCAP - 1 of its sensor.  The
         // balls are taken in chunk order (spatially coherent after slingbag_order);
@@ -211,13 +326,24 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         // a, added to the global trace with one coalesced FP32 atomic per row.
         auto flush = [&]() {
             const int nblk = (wave_max_all(kmax) + 64) >> 6;
+            uint32_t d1 = 0u, d0 = 0u;                   // running sums of the second differences
             for (int q = 0; q < nblk; ++q) {
                 float* const blk = tw + q * 64 * 64;
                 float* const mat = blk - 64;
                 float col[64];
                 wave_lds_sync();
+                if (qmode) {
+                    const uint32_t* const blku = twu + q * 64 * 64;
 #pragma unroll
-                for (int k = 0; k < 64; ++k) col[k] = blk[k * 64 + lane];
+                    for (int k = 0; k < 64; ++k) {
+                        d1 += blku[k * 64 + lane];
+                        d0 += d1;
+                        col[k] = (float)(int32_t)d0 * qeps;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 64; ++k) col[k] = blk[k * 64 + lane];
+                }
                 wave_lds_sync();
 #pragma unroll
                 for (int k = 0; k < 64; ++k) mat[lane * 65 + k] = col[k];
@@ -270,7 +396,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         };
         auto apply = [&](const FwdPair& f) {
             const bool part = f.in_tile;
-            const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
+            const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? (qmode ? (f.W >= 5 ? f.W + 2 : 6) : max(f.W, 3)) : f.W;
             if (rows <= UCAP) {
                 int tl = f.klo - o;
                 if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
@@ -278,10 +404,13 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                     if (part) o = f.klo - ((UCAP - rows) >> 1);
                     tl = f.klo - o;
                 }
-                // lanes without a window add zeros at rows 0..2
+                // lanes without a window add zeros at the first rows
                 const int tr = part ? tl : 0;
-                add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
-                if (part) kmax = max(kmax, tl + f.W - 1);
+                if (KERNEL == SB_KERNEL_UNIFORM && qmode)
+                    add_window_d2(twu + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg * qs : 0.f);
+                else
+                    add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
+                if (part) kmax = max(kmax, tl + (qmode ? rows : f.W) - 1);
             } else if (part) {
                 clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
             }

@@ -194,6 +194,61 @@ def test_single_ball_single_sensor():
     assert abs(y.sum()) < 1e-6 * np.abs(y).max()
 
 
+def _morton(wl):
+    order = synth.morton_order(wl.balls)
+    return with_(wl, balls=np.ascontiguousarray(wl.balls[:, order]))
+
+
+def test_window_lengths_two_to_forty():
+    """Uniform spheres from R = 0.005 mm to 0.75 mm: window lengths W = 2 .. 42 samples
+    (the short windows take the four-sample second-difference form), amplitudes over
+    three decades in one chunk."""
+    wl = tiny_scene(n_balls=600, n_sensors=70, seed=85)
+    b = wl.balls.copy()
+    rng = np.random.default_rng(85)
+    delta = wl.c / wl.fs
+    W = rng.integers(2, 43, size=b.shape[1])
+    b[3] = ((W - 2 + rng.uniform(0.05, 0.95, size=W.size)) * delta / 2).astype(np.float32)
+    b[4] = (10.0 ** rng.uniform(-3, 0, size=W.size)).astype(np.float32)
+    k0 = synth.record_start(0.060, 0.010, 0.8e-3, 0.5e-3)
+    n = synth.record_length_needed(0.060, 0.010, 0.8e-3, 0.5e-3, k0)
+    wl = _morton(with_(wl, balls=b, t0=k0 / wl.fs, n_samples=n))
+    Wk = np.floor(2 * wl.balls[3].astype(np.float64) / delta).astype(int) + 2
+    assert {2, 3, 4, 5, 6}.issubset(set(Wk.tolist()))
+    y, flags = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"window lengths 2..42 rel-L2 {err:.3e}")
+    assert flags == 0
+    assert err <= SIG_TOL
+
+
+def test_sensors_among_the_balls():
+    """Sensors inside the cloud's box (outside every ball), all among the first 64: the
+    wave holding them keeps the FP32 tile, the other waves take the integer one."""
+    wl = tiny_scene(n_balls=900, n_sensors=200, seed=86)
+    sens = wl.sensors.copy()
+    rng = np.random.default_rng(86)
+    inner = rng.choice(64, size=40, replace=False)     # all in the first 64-sensor wave
+    b = wl.balls.astype(np.float64)
+    for s in inner:
+        while True:
+            p = rng.uniform(-0.012, 0.012, size=3)
+            if np.min(np.linalg.norm(b[0:3] - p[:, None], axis=0) - b[3]) > 0.5e-3:
+                break
+        sens[:, s] = p.astype(np.float32)
+    k0 = 0
+    n = synth.record_length_needed(0.060, 0.010, 0.4e-3, 0.5e-3, k0)
+    wl = _morton(with_(wl, sensors=sens, t0=0.0, n_samples=n))
+    y, flags = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    err_in = rel_l2(y[:, inner], ref[:, inner])
+    _say(f"sensors among the balls rel-L2 {err:.3e} (inner sensors {err_in:.3e}) flags={flags}")
+    assert flags == 0
+    assert err <= SIG_TOL and err_in <= SIG_TOL
+
+
 def test_clipped_record_is_dropped_and_flagged():
     wl = tiny_scene(n_balls=50, n_sensors=10, seed=82)
     wl = with_(wl, n_samples=200, t0=wl.t0 + 150 / wl.fs)   # record too short: most traces clipped
@@ -326,7 +381,10 @@ def test_result_independent_of_order():
     y0, _ = gpu_forward(wl)
     ws = synth.apply_order(wl)
     y1, _ = gpu_forward(ws)
-    assert rel_l2(y1, y0) <= 1e-6
+    # The uniform sphere's integer tile rounds every sample to 2^-30 of its chunk's
+    # amplitude bound, and which balls share a chunk depends on the order: each run
+    # lies about 1e-6 (relative L2) from the exact signal, so the two may differ by twice that.
+    assert rel_l2(y1, y0) <= 3e-6
     rng = np.random.default_rng(8)
     res = rng.normal(size=y0.shape).astype(np.float32)
     g0 = gpu_adjoint(wl, res)

@@ -116,45 +116,55 @@ __device__ inline void add_window(float* c, int W, float x0, float rho, float C)
 // A and B, so every window's second differences sum back to exactly zero past
 // its end: all arithmetic is modulo 2^32 and the running sums return the exact
 // integer column as long as its true value fits in int32, which the caller's
-// choice of s guarantees.  Windows with W < 5 take four clamped samples (rows
-// 0 .. 5).  Rows: W + 2 for W >= 5, else 6.
-__device__ inline void add_window_d2(uint32_t* c, int W, float x0, float rho, float Cs) {
+// choice of s guarantees.  A window with W < 5 is written as one of length 5
+// (its samples from W on are exactly zero): samples 1 and 2 then define the
+// "ramp" through A = u_1 and B = u_2 - u_1.  Rows: max(W, 5) + 2.
+struct D2Win {
+    uint32_t d[7];   // added to rows 0, 1, 2 and w2 .. w2 + 3 of the window
+    int w2;          // max(W, 5) - 2
+};
+
+// round to nearest (halves up) in one conversion
+__device__ inline int round_rpi(float v) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+template <bool LONG>   // LONG: the caller knows W >= 5
+__device__ inline D2Win d2_window(int W, float x0, float rho, float Cs) {
     const float rr = rho * rho;
     auto sq = [&](float x) {
         const float q = __builtin_amdgcn_fmed3f(x, -rho, rho);
         return q * q;
     };
-    auto qn = [](float v) { return (uint32_t)__float2int_rn(v); };
-    if (W >= 5) {
-        const float xa = x0 - (float)(W - 2);             // boundary W-2 (exact in FP32)
-        const float qa = sq(xa), qb = sq(xa - 1.f);
-        const uint32_t u0 = qn(Cs * (rr - sq(x0 - 1.f)));
-        const uint32_t a = qn(Cs * fmaf(2.f, x0, -3.f));   // sample 1 of the ramp C (2 x_j - 1)
-        const uint32_t b = qn(-2.f * Cs);                  // ramp step
-        const uint32_t e1 = qn(Cs * (qa - qb)), e2 = qn(Cs * (qb - rr));
-        const uint32_t last = a + b * (uint32_t)(W - 4);   // ramp sample W-3
-        uint32_t* const p1 = c + (W - 2) * 64;
-        const uint32_t o0 = c[0], o1 = c[64], o2 = c[128];
-        const uint32_t o3 = p1[0], o4 = p1[64], o5 = p1[128], o6 = p1[192];
-        c[0] = o0 + u0;
-        c[64] = o1 + a - 2u * u0;
-        c[128] = o2 + b - a + u0;
-        p1[0] = o3 + e1 - last - b;
-        p1[64] = o4 + e2 - 2u * e1 + last;
-        p1[128] = o5 + e1 - 2u * e2;
-        p1[192] = o6 + e2;
+    auto qn = [](float v) { return (uint32_t)round_rpi(v); };
+    const int Wp = LONG ? W : max(W, 5);
+    const float q1 = sq(x0 - 1.f);
+    float va, vb;                                        // sample 1 and the step to sample 2 (units of C)
+    if (LONG || W >= 5) {
+        va = fmaf(2.f, x0, -3.f);                        // C (2 x_1 - 1)
+        vb = -2.f;
     } else {
-        const float q1 = sq(x0 - 1.f), q2 = sq(x0 - 2.f), q3 = sq(x0 - 3.f), q4 = sq(x0 - 4.f);
-        const uint32_t u0 = qn(Cs * (rr - q1)), u1 = qn(Cs * (q1 - q2));
-        const uint32_t u2 = qn(Cs * (q2 - q3)), u3 = qn(Cs * (q3 - q4));
-        const uint32_t o0 = c[0], o1 = c[64], o2 = c[128], o3 = c[192], o4 = c[256], o5 = c[320];
-        c[0] = o0 + u0;
-        c[64] = o1 + u1 - 2u * u0;
-        c[128] = o2 + u2 - 2u * u1 + u0;
-        c[192] = o3 + u3 - 2u * u2 + u1;
-        c[256] = o4 + u2 - 2u * u3;
-        c[320] = o5 + u3;
+        const float q2 = sq(x0 - 2.f), q3 = sq(x0 - 3.f);
+        va = q1 - q2;
+        vb = (q2 - q3) - va;
     }
+    const float xa = x0 - (float)(Wp - 2);               // boundary Wp-2 (exact in FP32)
+    const float qa = sq(xa), qb = sq(xa - 1.f);          // boundary Wp lies below -rho
+    const uint32_t u0 = qn(Cs * (rr - q1)), a = qn(Cs * va), b = qn(Cs * vb);
+    const uint32_t e1 = qn(Cs * (qa - qb)), e2 = qn(Cs * (qb - rr));
+    const uint32_t last = a + b * (uint32_t)(Wp - 4);    // ramp sample Wp-3
+    D2Win r;
+    r.d[0] = u0;
+    r.d[1] = a - 2u * u0;
+    r.d[2] = b - a + u0;
+    r.d[3] = e1 - last - b;
+    r.d[4] = e2 - 2u * e1 + last;
+    r.d[5] = e1 - 2u * e2;
+    r.d[6] = e2;
+    r.w2 = Wp - 2;
+    return r;
 }
 
 // Per-pair quantities of one ball for the wave's 64 sensors (one per lane).
@@ -240,8 +250,9 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 // bound of the chunk's contribution to any sample: |v| <= |P delta/4| (2 rho + 1) / r
                 // for every tile window, with r at least the distance from the sensor to the
                 // box of the centres
-                // (tile windows: W + 2 <= UCAP rows with W = floor(2 rho) + 2, as in the pair set-up)
-                const bool in_tile = tid < nb && bl.rho >= 0.0 && (int)(2.0 * fmin(bl.rho, 1.0e6)) + 4 <= UCAP;
+                // (tile windows: max(W, 5) + 2 <= UCAP rows with W = floor(2 rho) + 2, as in the
+                // pair set-up)
+                const bool in_tile = tid < nb && bl.rho >= 0.0 && max((int)(2.0 * fmin(bl.rho, 1.0e6)) + 2, 5) + 2 <= UCAP;
                 const float inf = __builtin_huge_valf();
                 const float lo[3] = {in_tile ? (float)bl.x : inf, in_tile ? (float)bl.y : inf,
                                      in_tile ? (float)bl.z : inf};
@@ -375,9 +386,8 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         };
 
         // pair set-up of ball i for this wave's sensors
-        auto prep = [&](int i) {
+        auto setup = [&](const BallF& bl) {
             FwdPair f;
-            const BallF bl = sball[i];
             const bool valid = bl.rho >= 0.0;
             const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
             const bool too_long = valid && h >= 1.0e6;       // window longer than any record
@@ -394,9 +404,10 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             f.rhof = bl.rhof;
             return f;
         };
+        auto prep = [&](int i) { return setup(sball[i]); };
         auto apply = [&](const FwdPair& f) {
             const bool part = f.in_tile;
-            const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? (qmode ? (f.W >= 5 ? f.W + 2 : 6) : max(f.W, 3)) : f.W;
+            const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
             if (rows <= UCAP) {
                 int tl = f.klo - o;
                 if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
@@ -406,21 +417,85 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 }
                 // lanes without a window add zeros at the first rows
                 const int tr = part ? tl : 0;
-                if (KERNEL == SB_KERNEL_UNIFORM && qmode)
-                    add_window_d2(twu + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg * qs : 0.f);
-                else
-                    add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
-                if (part) kmax = max(kmax, tl + (qmode ? rows : f.W) - 1);
+                add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
+                if (part) kmax = max(kmax, tl + f.W - 1);
             } else if (part) {
                 clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
             }
         };
-        // software pipeline: the set-up of ball i+1 overlaps the tile update of ball i
-        FwdPair cur = prep(0);
-        for (int i = 0; i < nb; ++i) {
-            const FwdPair nxt = prep(min(i + 1, nb - 1));
-            apply(cur);
-            cur = nxt;
+        if (KERNEL == SB_KERNEL_UNIFORM && qmode) {
+            // Integer tile.  Per ball: place this ball's window (flushing if needed),
+            // issue the seven row reads, run the next ball's FP64 set-up while the reads
+            // are in flight, then write the seven rows.  Balls are read from LDS two
+            // ahead, so the set-up never waits for the row reads.
+            FwdPair cur = prep(0);
+            BallF bn = sball[min(1, nb - 1)];
+            for (int i = 0; i < nb; ++i) {
+                const BallF bnn = sball[min(i + 2, nb - 1)];
+                const bool part = cur.in_tile;
+                const int rows = max(cur.W, 5) + 2;           // the same in every lane
+                const bool in_lds = rows <= UCAP;
+                int tr = 0;                                   // the window's first tile row
+                if (in_lds) {
+                    // the loop's one flush site: flush and re-centre when this ball's
+                    // window leaves some lane's column
+                    int tl = cur.klo - o;
+                    if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
+                        flush();
+                        if (part) o = cur.klo - ((UCAP - rows) >> 1);
+                        tl = cur.klo - o;
+                    }
+                    if (part) kmax = max(kmax, tl + rows - 1);
+                    tr = part ? tl : 0;
+                }
+                FwdPair nxt;
+                if (cur.W >= 5 && in_lds) {
+                    // common case, one basic block: the window's values, the next ball's
+                    // set-up and the row updates interleave
+                    const D2Win dw = d2_window<true>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
+                    uint32_t* const c0 = twu + tr * 64 + lane;
+                    uint32_t* const c1 = c0 + dw.w2 * 64;
+                    const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
+                    const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
+                    nxt = setup(bn);
+                    c0[0] = o0 + dw.d[0];
+                    c0[64] = o1 + dw.d[1];
+                    c0[128] = o2 + dw.d[2];
+                    c1[0] = o3 + dw.d[3];
+                    c1[64] = o4 + dw.d[4];
+                    c1[128] = o5 + dw.d[5];
+                    c1[192] = o6 + dw.d[6];
+                } else {
+                    if (in_lds) {
+                        const D2Win dw = d2_window<false>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
+                        uint32_t* const c0 = twu + tr * 64 + lane;
+                        uint32_t* const c1 = c0 + dw.w2 * 64;
+                        const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
+                        const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
+                        c0[0] = o0 + dw.d[0];
+                        c0[64] = o1 + dw.d[1];
+                        c0[128] = o2 + dw.d[2];
+                        c1[0] = o3 + dw.d[3];
+                        c1[64] = o4 + dw.d[4];
+                        c1[128] = o5 + dw.d[5];
+                        c1[192] = o6 + dw.d[6];
+                    } else if (part) {
+                        clipped |= add_window_global<KERNEL>(out_row, cur.klo, p.T, cur.W, cur.xg, cur.rhof, cur.Cg);
+                    }
+                    nxt = setup(bn);
+                }
+                cur = nxt;
+                bn = bnn;
+            }
+        } else {
+            // FP32 tile; software pipeline: the set-up of ball i+1 overlaps the tile
+            // update of ball i
+            FwdPair cur = prep(0);
+            for (int i = 0; i < nb; ++i) {
+                const FwdPair nxt = prep(min(i + 1, nb - 1));
+                apply(cur);
+                cur = nxt;
+            }
         }
         flush();
     }

@@ -167,6 +167,18 @@ __device__ inline D2Win d2_window(int W, float x0, float rho, float Cs) {
     return r;
 }
 
+// A chunk ball as staged in LDS for the pair set-up: what depends on the ball only
+// is computed once per ball instead of once per pair.
+struct BallS {
+    double x, y, z;   // deformed centre (m)
+    double c1;        // t0 fs + h - 1/2: the window starts at sample floor(r / delta - c1)
+    double Rd;        // uniform sphere: R_f (m), the sensor must lie outside; Gaussian ball: 0
+    float amp;        // amplitude scale of the trace
+    float rhof;       // rho = R_f / delta (samples)
+    float hf;         // half-width h of the window: rho (uniform) or kGaussCut rho (Gaussian)
+    int Wc;           // window length W = floor(2 h) + 2; 0: no ball; -1: longer than any record
+};
+
 // Per-pair quantities of one ball for the wave's 64 sensors (one per lane).
 struct FwdPair {
     float Cg, xg;    // amplitude and boundary 0
@@ -209,7 +221,7 @@ template <int NW, int G, int UCAP, int KERNEL>
 __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
     static_assert(UCAP % 64 == 0, "tile length must be a multiple of 64");
     static_assert(G == 64 * NW, "one ball per thread when staging");
-    __shared__ BallF sball[G];
+    __shared__ BallS sball[G];
     __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
     __shared__ float s_box[NW][8];                    // per wave: centre box of the chunk's tile balls, amplitude sum
     __shared__ float tile[NW][(UCAP + 1) * 64];     // per wave: a pad row, then UCAP rows of 64 sensors
@@ -245,7 +257,21 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 bl.rhof = -1.f;
                 bl.amp = 0.f;
             }
-            sball[tid] = bl;
+            {
+                BallS bs;
+                const bool valid = bl.rho >= 0.0;
+                const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
+                bs.x = bl.x;
+                bs.y = bl.y;
+                bs.z = bl.z;
+                bs.c1 = p.t0fs + h - 0.5;
+                bs.Rd = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho * (double)p.delta : 0.0;
+                bs.amp = bl.amp;
+                bs.rhof = bl.rhof;
+                bs.hf = (float)h;
+                bs.Wc = !valid ? 0 : (h >= 1.0e6 ? -1 : (int)(2.0 * h) + 2);
+                sball[tid] = bs;
+            }
             if (KERNEL == SB_KERNEL_UNIFORM) {
                 // bound of the chunk's contribution to any sample: |v| <= |P delta/4| (2 rho + 1) / r
                 // for every tile window, with r at least the distance from the sensor to the
@@ -386,22 +412,25 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         };
 
         // pair set-up of ball i for this wave's sensors
-        auto setup = [&](const BallF& bl) {
+        auto setup = [&](const BallS& bs) {
             FwdPair f;
-            const bool valid = bl.rho >= 0.0;
-            const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
-            const bool too_long = valid && h >= 1.0e6;       // window longer than any record
-            const int Wb = (int)(2.0 * fmin(fmax(h, 0.0), 1.0e6)) + 2;
-            f.W = __builtin_amdgcn_readfirstlane(Wb);
-            const PairWin<KERNEL> w = pair_window<KERNEL>(p, bl.rho, bl.x - sx, bl.y - sy, bl.z - sz);
+            const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
+            const bool valid = Wc != 0, too_long = Wc < 0;
+            f.W = Wc > 0 ? Wc : 5;                           // no window: zeros at the first rows
+            float ri;
+            const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
+            const bool ok = r > bs.Rd;                       // outside the uniform ball (r > 0: Gaussian)
+            const double u = fma(r, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
+            const double kl = floor(u);
+            const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
             const bool use = active && valid && !too_long;
-            geometry |= use && !w.ok;
-            clipped |= (active && too_long) || (use && w.ok && !w.in_range);
-            f.in_tile = use && w.ok && w.in_range;            // the window exists (placed at apply)
-            f.Cg = bl.amp * w.ri;                            // amp holds the amplitude scale (staging)
-            f.xg = (float)w.a0;
-            f.klo = w.klo;
-            f.rhof = bl.rhof;
+            geometry |= use && !ok;
+            clipped |= (active && too_long) || (use && ok && !in_range);
+            f.in_tile = use && ok && in_range;               // the window exists (placed at apply)
+            f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
+            f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
+            f.klo = in_range ? (int)kl : 0;
+            f.rhof = bs.rhof;
             return f;
         };
         auto prep = [&](int i) { return setup(sball[i]); };
@@ -429,9 +458,9 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             // are in flight, then write the seven rows.  Balls are read from LDS two
             // ahead, so the set-up never waits for the row reads.
             FwdPair cur = prep(0);
-            BallF bn = sball[min(1, nb - 1)];
+            BallS bn = sball[min(1, nb - 1)];
             for (int i = 0; i < nb; ++i) {
-                const BallF bnn = sball[min(i + 2, nb - 1)];
+                const BallS bnn = sball[min(i + 2, nb - 1)];
                 const bool part = cur.in_tile;
                 const int rows = max(cur.W, 5) + 2;           // the same in every lane
                 const bool in_lds = rows <= UCAP;

@@ -363,6 +363,12 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         // a, added to the global trace with one coalesced FP32 atomic per row.
         auto flush = [&]() {
             const int nblk = (wave_max_all(kmax) + 64) >> 6;
+            // When every lane's touched samples o .. o + kmax lie inside the record (the usual
+            // case), the rows go out without a per-sample range test: one 64-bit row address
+            // per sensor, and the atomics skip the zero samples.
+            const bool inside = __all(kmax < 0 || (o >= 0 && o + kmax < p.T));
+            const uintptr_t rowp = reinterpret_cast<uintptr_t>(p.signals) +
+                                   (uintptr_t)(row_off + (int64_t)o) * sizeof(float);
             uint32_t d1 = 0u, d0 = 0u;                   // running sums of the second differences
             for (int q = 0; q < nblk; ++q) {
                 float* const blk = tw + q * 64 * 64;
@@ -385,21 +391,38 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
 #pragma unroll
                 for (int k = 0; k < 64; ++k) mat[lane * 65 + k] = col[k];
                 wave_lds_sync();
+                if (inside) {
 #pragma unroll
-                for (int a0 = 0; a0 < 64; a0 += 8) {
-                    float v[8];                                  // sample q*64 + lane of sensors a0 .. a0+7
+                    for (int a0 = 0; a0 < 64; a0 += 8) {
+                        float v[8];                              // sample q*64 + lane of sensors a0 .. a0+7
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
+                        for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int a = a0 + u;
-                        const int act_a = __builtin_amdgcn_readlane((int)active, a);
-                        const int k = __builtin_amdgcn_readlane(o, a) + q * 64 + lane;
-                        const int64_t ra = ((int64_t)__builtin_amdgcn_readlane((int)(row_off >> 32), a) << 32) |
-                                           (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)row_off, a);
-                        if (v[u] != 0.f && act_a) {
-                            if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + ra + k, v[u]);
-                            else clipped = true;
+                        for (int u = 0; u < 8; ++u) {
+                            const int a = a0 + u;
+                            const uint64_t pa =
+                                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(rowp >> 32), a) << 32) |
+                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rowp, a);
+                            if (v[u] != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(pa) + (q * 64 + lane), v[u]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int a0 = 0; a0 < 64; a0 += 8) {
+                        float v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int a = a0 + u;
+                            const int act_a = __builtin_amdgcn_readlane((int)active, a);
+                            const int k = __builtin_amdgcn_readlane(o, a) + q * 64 + lane;
+                            const int64_t ra = ((int64_t)__builtin_amdgcn_readlane((int)(row_off >> 32), a) << 32) |
+                                               (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)row_off, a);
+                            if (v[u] != 0.f && act_a) {
+                                if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + ra + k, v[u]);
+                                else clipped = true;
+                            }
                         }
                     }
                 }

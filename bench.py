@@ -13,7 +13,8 @@ Fibonacci hemisphere, 4,096 samples at 40 MHz.
 Prints ONE JSON line.  `value` is ball*sensor*frame pairs per second through
 forward + adjoint (GPairs/s).  The roofline object reports the dominant kernel
 in vector-ALU lane operations against the chip's lane-operation peak (the path has no dense contraction and its
-DRAM traffic is small next to its arithmetic); the cpu_baseline object times
+DRAM traffic is small next to its arithmetic), counting the closed forms the
+kernels evaluate, with the direct per-sample evaluation beside it; the cpu_baseline object times
 the FP64 CPU oracle on the host cores over the same workload.
 """
 
@@ -47,15 +48,35 @@ def workloads():
     }
 
 
-def op_model(wl):
-    """Algorithmic vector-ALU lane operations of one forward and one adjoint launch.
+# Algorithmic lane operations per pair of the closed forms the uniform-sphere
+# kernels evaluate (counted from the formulas, not from the compiled code):
+#   geometry (both kernels): 40 -- FP64 distance with its refinement, window start,
+#     fraction, 1/r, validity;
+#   forward window: 42 -- five sample values of the window (sample 0, the ramp's first
+#     value and step, the two end samples; shift, clamp, square, difference, scale and
+#     round: 25), the seven second differences (10 integer operations), the seven tile
+#     additions (7);
+#   adjoint window: 36 -- boundary count (4), prefix differences T0 and T1 (4), the
+#     closed-form sums S_t, S_w, S_r (13), the pair's contributions to dL/dr, dL/dR,
+#     dL/dP and the direction (15).
+# The flush (running sums, scale and one atomic per touched sample) and the residual
+# row staging are not counted.
+FWD_PAIR_OPS = 40 + 42
+ADJ_PAIR_OPS = 40 + 36
 
-    Per (ball, sensor, frame) pair with a window of W samples (W = floor(2 R_f/delta) + 2
-    for the uniform sphere), counting the direct evaluation of the method: 40 for the
-    FP64 pair geometry in each kernel, 8 per sample in the forward (clamp, square,
-    difference, scale, accumulate) and 14 per sample in the adjoint (residual difference
-    and the three weighted sums).  The kernels evaluate the interior of each window in
-    closed form and execute fewer operations than this count.
+
+def op_model(wl):
+    """Lane operations of one forward and one adjoint launch.
+
+    `forward` / `adjoint`: the closed forms the kernels evaluate (FWD_PAIR_OPS,
+    ADJ_PAIR_OPS per pair) for the uniform sphere.  `direct_forward` /
+    `direct_adjoint`: the direct evaluation of the method per sample -- 40 for the FP64
+    pair geometry in each kernel, 8 per sample in the forward (clamp, square,
+    difference, scale, accumulate) and 14 per sample in the adjoint (residual
+    difference and the three weighted sums) over a window of W samples (W = floor(2
+    R_f/delta) + 2); the closed forms execute fewer operations than this count, so it
+    can exceed the peak.  The Gaussian ball has no closed form: both models are the
+    direct one.
     """
     import numpy as np
     delta = wl.c / wl.fs
@@ -76,9 +97,13 @@ def op_model(wl):
             W = np.floor(2.0 * Rf / delta) + 2.0
             sumW += float(W.sum()) * S
             pairs += len(R) * S
-    fwd = 40.0 * pairs + 8.0 * sumW
-    adj = 40.0 * pairs + 14.0 * sumW
-    return {"forward": fwd, "adjoint": adj, "pairs": pairs, "mean_window": sumW / max(pairs, 1)}
+    dfwd = 40.0 * pairs + 8.0 * sumW
+    dadj = 40.0 * pairs + 14.0 * sumW
+    closed = wl.kernel == 0
+    return {"forward": FWD_PAIR_OPS * pairs if closed else dfwd,
+            "adjoint": ADJ_PAIR_OPS * pairs if closed else dadj,
+            "direct_forward": dfwd, "direct_adjoint": dadj,
+            "pairs": pairs, "mean_window": sumW / max(pairs, 1)}
 
 
 def _fourier_frames(wl, balls_np, deform_np):
@@ -401,6 +426,7 @@ def main():
     per_kernel = {k: (ms / n if n else None) for k, (ms, n) in kt.items()}
     dom = max(("forward", "adjoint"), key=lambda k: per_kernel[k] or 0.0)
     achieved = fm[dom] / (per_kernel[dom] * 1e-3) / 1e12
+    achieved_direct = fm["direct_" + dom] / (per_kernel[dom] * 1e-3) / 1e12
     # HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE /
     # WRITE_SIZE record of this workload and instance (null once its sources change)
     from paper_2412_03898_amd import profsum
@@ -429,7 +455,10 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                      "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
                      "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic, "traffic_unit": "B/launch",
-                     "ops_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3)},
+                     "ops_per_launch": fm[dom], "mean_window": round(fm["mean_window"], 3),
+                     "direct_model": {"ops_per_launch": fm["direct_" + dom],
+                                      "achieved": round(achieved_direct, 3),
+                                      "frac": round(achieved_direct / ALU_PEAK_TOPS, 4)}},
         "kernel_ms": {k: (round(v, 4) if v is not None else None) for k, v in per_kernel.items()},
         "graph_ms_per_step": None if ms_graph is None else round(ms_graph, 4),
         "device_flags": flags,

@@ -107,8 +107,10 @@ __device__ inline void fourier_basis(float t, int K, double* fb) {
 }
 
 // Same values computed cooperatively: lane k < 2K of the calling wave writes entry
-// k of an LDS array (the values are the same for every lane of a frame).
-__device__ inline void fourier_basis_lanes(float t, int K, double* fb, int lane) {
+// k of an LDS array (the values are the same for every lane of a frame).  Kept out
+// of line: the kernels call it once per frame, and inlined, the FP64 constants of
+// sincospi are hoisted out of their loops into registers that the pair loops need.
+__device__ __noinline__ void fourier_basis_lanes(float t, int K, double* fb, int lane) {
     if (lane < 2 * K) {
         const int k = lane / 2 + 1;
         double s, c;
@@ -119,6 +121,20 @@ __device__ inline void fourier_basis_lanes(float t, int K, double* fb, int lane)
 
 // H of attribute a of ball b at time t (Eq. 2 or the Fourier series), in FP64 so
 // that deformed positions and sizes carry no FP32 rounding into the arrival time.
+// Eq. 2 sum of one attribute (coefficients d, stride B).  Out of line for the same
+// reason as fourier_basis_lanes (the FP64 constants of exp).
+__device__ __noinline__ double gauss_basis_H(const float* d, int64_t B, int n_terms, float t) {
+    double h = 0.0;
+    for (int n = 0; n < n_terms; ++n) {
+        const double w = d[(int64_t)(3 * n) * B];
+        const double th = d[(int64_t)(3 * n + 1) * B];
+        const double sg = d[(int64_t)(3 * n + 2) * B];
+        const double dt = (double)t - th;
+        h = fma(w, exp(-dt * dt / (2.0 * sg * sg)), h);
+    }
+    return h;
+}
+
 __device__ inline double eval_H(const OpParams& p, int64_t b, int a, float t, const double* fb) {
     if (p.basis == SB_BASIS_STATIC) return 0.0;
     const float* d = p.deform + (int64_t)a * p.M * p.B + b;
@@ -126,13 +142,7 @@ __device__ inline double eval_H(const OpParams& p, int64_t b, int a, float t, co
     if (p.basis == SB_BASIS_FOURIER) {
         for (int m = 0; m < p.M; ++m) h = fma((double)d[(int64_t)m * p.B], fb[m], h);
     } else {
-        for (int n = 0; n < p.n_terms; ++n) {
-            const double w = d[(int64_t)(3 * n) * p.B];
-            const double th = d[(int64_t)(3 * n + 1) * p.B];
-            const double sg = d[(int64_t)(3 * n + 2) * p.B];
-            const double dt = (double)t - th;
-            h = fma(w, exp(-dt * dt / (2.0 * sg * sg)), h);
-        }
+        h = gauss_basis_H(d, p.B, p.n_terms, t);
     }
     return h;
 }

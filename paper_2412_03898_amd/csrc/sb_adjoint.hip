@@ -489,16 +489,36 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                                 const int k = klo + m;
                                 return (k >= 0 && k < p.T) ? rres[k] : 0.f;
                             };
-                            const float q0 = at(0), qM = at(M);
+                            float q0, qM;
                             double g0 = 0.0, g1 = 0.0;
-                            for (int m0 = 1; m0 < M; m0 += 8) {
-                                float v[8];
+                            if (klo >= 0 && klo + M < p.T) {
+                                // window inside the record (the usual case): one base address,
+                                // immediate offsets, no per-sample range test
+                                const float* w = rres + klo;
+                                q0 = w[0];
+                                qM = w[M];
+                                for (int m0 = 1; m0 < M; m0 += 8) {
+                                    float v[8];
 #pragma unroll
-                                for (int u = 0; u < 8; ++u) v[u] = (m0 + u < M) ? at(m0 + u) : 0.f;
+                                    for (int u = 0; u < 8; ++u) v[u] = (m0 + u < M) ? w[m0 + u] : 0.f;
 #pragma unroll
-                                for (int u = 0; u < 8; ++u) {
-                                    g0 += (double)v[u];
-                                    g1 = fma((double)(m0 + u), (double)v[u], g1);
+                                    for (int u = 0; u < 8; ++u) {
+                                        g0 += (double)v[u];
+                                        g1 = fma((double)(m0 + u), (double)v[u], g1);
+                                    }
+                                }
+                            } else {
+                                q0 = at(0);
+                                qM = at(M);
+                                for (int m0 = 1; m0 < M; m0 += 8) {
+                                    float v[8];
+#pragma unroll
+                                    for (int u = 0; u < 8; ++u) v[u] = (m0 + u < M) ? at(m0 + u) : 0.f;
+#pragma unroll
+                                    for (int u = 0; u < 8; ++u) {
+                                        g0 += (double)v[u];
+                                        g1 = fma((double)(m0 + u), (double)v[u], g1);
+                                    }
                                 }
                             }
                             const double xMg = a0d - (double)M, x1g = a0d - 1.0;

@@ -497,16 +497,21 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                                 const float* w = rres + klo;
                                 q0 = w[0];
                                 qM = w[M];
+                                // FP32 sums of at most a window's samples (each product m r_m is
+                                // exact in FP32 up to rounding of r_m), widened for the closed form
+                                float h0 = 0.f, h1 = 0.f;
                                 for (int m0 = 1; m0 < M; m0 += 8) {
                                     float v[8];
 #pragma unroll
                                     for (int u = 0; u < 8; ++u) v[u] = (m0 + u < M) ? w[m0 + u] : 0.f;
 #pragma unroll
                                     for (int u = 0; u < 8; ++u) {
-                                        g0 += (double)v[u];
-                                        g1 = fma((double)(m0 + u), (double)v[u], g1);
+                                        h0 += v[u];
+                                        h1 = fmaf((float)(m0 + u), v[u], h1);
                                     }
                                 }
+                                g0 = h0;
+                                g1 = h1;
                             } else {
                                 q0 = at(0);
                                 qM = at(M);

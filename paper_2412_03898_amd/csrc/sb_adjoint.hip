@@ -491,24 +491,29 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                             };
                             float q0, qM;
                             double g0 = 0.0, g1 = 0.0;
-                            if (klo >= 0 && klo + M < p.T) {
-                                // window inside the record (the usual case): one base address,
-                                // immediate offsets, no per-sample range test
+                            if (klo >= 0 && klo + M + 8 < p.T) {
+                                // window and one batch beyond it inside the record (the usual
+                                // case): one base address, immediate offsets, every load of a
+                                // batch unconditional and the samples past the window masked
                                 const float* w = rres + klo;
                                 q0 = w[0];
                                 qM = w[M];
-                                // FP32 sums of at most a window's samples (each product m r_m is
-                                // exact in FP32 up to rounding of r_m), widened for the closed form
+                                // FP32 sums of at most a window's samples, widened for the
+                                // closed form
                                 float h0 = 0.f, h1 = 0.f;
                                 for (int m0 = 1; m0 < M; m0 += 8) {
                                     float v[8];
 #pragma unroll
-                                    for (int u = 0; u < 8; ++u) v[u] = (m0 + u < M) ? w[m0 + u] : 0.f;
+                                    for (int u = 0; u < 8; ++u) v[u] = w[m0 + u];
+                                    float b0 = 0.f, b1 = 0.f;     // sum r and sum u r over the batch
 #pragma unroll
                                     for (int u = 0; u < 8; ++u) {
-                                        h0 += v[u];
-                                        h1 = fmaf((float)(m0 + u), v[u], h1);
+                                        const float x = (m0 + u < M) ? v[u] : 0.f;
+                                        b0 += x;
+                                        b1 = fmaf((float)u, x, b1);
                                     }
+                                    h0 += b0;
+                                    h1 = fmaf((float)m0, b0, h1 + b1);
                                 }
                                 g0 = h0;
                                 g1 = h1;

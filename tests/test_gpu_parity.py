@@ -194,6 +194,27 @@ def test_single_ball_single_sensor():
     assert abs(y.sum()) < 1e-6 * np.abs(y).max()
 
 
+def test_adjoint_windows_outside_the_staged_row_and_at_the_record_end():
+    """Unordered balls (each chunk spans the whole cube, so almost every window lies outside
+    the staged residual row and takes the global-memory path) and a record cut 40 samples
+    before the latest window ends: windows near, across and past the last sample."""
+    wl = tiny_scene(n_balls=700, n_sensors=70, seed=87)
+    b = wl.balls.astype(np.float64)
+    S = wl.sensors.astype(np.float64)
+    delta = wl.c / wl.fs
+    r = np.sqrt(((b[0:3, :, None] - S[:, None, :]) ** 2).sum(0))
+    rho = b[3] / delta
+    kl = np.floor(r / delta - wl.t0 * wl.fs - rho[:, None] + 0.5).astype(int)
+    end = kl + (np.floor(2 * rho).astype(int) + 2)[:, None]
+    T = int(end.max()) - 40
+    assert (end > T).sum() > 5 and (kl >= T).sum() > 0
+    wl = with_(wl, n_samples=T)
+    rng = np.random.default_rng(9)
+    res = rng.normal(size=(1, S.shape[1], T)).astype(np.float32)
+    _say(f"adjoint unordered, record cut at T={T}")
+    assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+
+
 def _morton(wl):
     order = synth.morton_order(wl.balls)
     return with_(wl, balls=np.ascontiguousarray(wl.balls[:, order]))

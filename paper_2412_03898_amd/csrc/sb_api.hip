@@ -176,12 +176,24 @@ static void fill_forward(OpParams& p, const sb_config* cfg, const sb_batch* batc
                          const TileCfg& tc) {
     fill_common(p, cfg, batch, sh);
     p.n_sblocks = (int32_t)((sh.S + 64 * tc.nw - 1) / (64 * tc.nw));
+    // Large launches stage each (frame, chunk) once for several sensor blocks, keeping
+    // at least kFwdItemsPerSlot items per resident block (about 512 on the chip).
+    constexpr int64_t kFwdItemsPerSlot = 16, kFwdSlots = 512;
+    int64_t chunk_frames = 0;
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        const Scene& s = p.scenes[i];
+        chunk_frames += (int64_t)s.n_frames * ((s.n_balls + tc.g - 1) / tc.g);
+    }
+    int64_t per = chunk_frames * p.n_sblocks / (kFwdItemsPerSlot * kFwdSlots);
+    per = per < 1 ? 1 : (per > p.n_sblocks ? p.n_sblocks : per);
+    p.sb_per_item = (int32_t)per;
+    p.n_sitems = (p.n_sblocks + p.sb_per_item - 1) / p.sb_per_item;
     int64_t items = 0;
     for (int i = 0; i < batch->n_scenes; ++i) {
         Scene& s = p.scenes[i];
         s.n_groups = (s.n_balls + tc.g - 1) / tc.g;
         s.item0 = items;
-        items += (int64_t)s.n_frames * s.n_groups * p.n_sblocks;
+        items += (int64_t)s.n_frames * s.n_groups * p.n_sitems;
     }
     p.n_items = items;
 }

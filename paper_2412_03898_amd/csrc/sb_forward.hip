@@ -300,230 +300,219 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         }
         __syncthreads();
 
-        const int s = it.sblock * 64 * NW + wid * 64 + lane;
-        const bool active = s < p.S;
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-        if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
-        const int64_t row_off = ((int64_t)gf * p.S + (active ? s : 0)) * p.T;   // this lane's trace row
-        float* out_row = p.signals + row_off;
+        // the item's sensor blocks, one after the other, against the staged chunk
+        const int sb_end = min(it.sblock + p.sb_per_item, p.n_sblocks);
+        for (int sbk = it.sblock; sbk < sb_end; ++sbk) {
+            const int s = sbk * 64 * NW + wid * 64 + lane;
+            const bool active = s < p.S;
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
+            const int64_t row_off = ((int64_t)gf * p.S + (active ? s : 0)) * p.T;   // this lane's trace row
+            float* out_row = p.signals + row_off;
 
-        // Uniform sphere: the tile holds second differences in units of 1/qs (add_window_d2)
-        // when a per-lane scale qs keeps every column within int32; qs = 2^30 r_min / sum,
-        // with r_min the distance from the sensor to the box of the tile balls' centres.
-        // A wave whose sensors come within a quarter of the box's far distance (the bound
-        // would cost precision) keeps the FP32 tile for this chunk.
-        float qs = 1.f, qeps = 1.f;
-        bool qmode = false;
-        if (KERNEL == SB_KERNEL_UNIFORM) {
-            float lo[3], hi[3], sum = 0.f;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = s_box[0][a];
-                hi[a] = s_box[0][3 + a];
-            }
-            sum = s_box[0][6];
-#pragma unroll
-            for (int w = 1; w < NW; ++w) {
-#pragma unroll
+            // Uniform sphere: the tile holds second differences in units of 1/qs (add_window_d2)
+            // when a per-lane scale qs keeps every column within int32; qs = 2^30 r_min / sum,
+            // with r_min the distance from the sensor to the box of the tile balls' centres.
+            // A wave whose sensors come within a quarter of the box's far distance (the bound
+            // would cost precision) keeps the FP32 tile for this chunk.
+            float qs = 1.f, qeps = 1.f;
+            bool qmode = false;
+            if (KERNEL == SB_KERNEL_UNIFORM) {
+                float lo[3], hi[3], sum = 0.f;
+    #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    lo[a] = fminf(lo[a], s_box[w][a]);
-                    hi[a] = fmaxf(hi[a], s_box[w][3 + a]);
+                    lo[a] = s_box[0][a];
+                    hi[a] = s_box[0][3 + a];
                 }
-                sum += s_box[w][6];
-            }
-            bool ok = true;
-            if (active) {
-                if (!(sum < __builtin_huge_valf())) {
-                    ok = false;                          // a non-finite amplitude in the chunk
-                } else if (sum > 0.f && lo[0] <= hi[0]) {
-                    double dmin, dmax;
-                    box_distance_range(lo, hi, sx, sy, sz, dmin, dmax);
-                    qs = (float)(1073741824.0 * dmin / (double)sum);
-                    ok = dmin > 0.25 * dmax && qs > 0.f && qs < __builtin_huge_valf();
-                    qeps = 1.f / qs;
-                }                                        // else: every tile amplitude is zero
-            }
-            qmode = __all(ok);
-        }
-        uint32_t* const twu = reinterpret_cast<uint32_t*>(tw);
-
-        // Each lane's column covers samples o .. o + UCAP - 1 of its sensor.  The
-        // balls are taken in chunk order (spatially coherent after slingbag_order);
-        // when a window does not fit its column in some lane, the wave flushes the
-        // tile and re-centres every lane's column on that ball's window.
-        int o = -(1 << 30);          // no column yet: the first window triggers the set-up
-        int kmax = -1;               // last tile row written (wave-wide max at the flush)
-
-        // ---- flush, per touched 64-sample block q: each lane reads its column
-        // (64 samples of its sensor) into registers and writes it back as row
-        // `lane` of a 64 x 65 matrix that starts 64 floats before the block (in
-        // the previous, already flushed block, or the pad row before the tile); the
-        // row stride of 65 keeps both the row writes and the column reads of the
-        // matrix conflict-free.  Row a then holds 64 consecutive samples of sensor
-        // a, added to the global trace with one coalesced FP32 atomic per row.
-        auto flush = [&]() {
-            const int nblk = (wave_max_all(kmax) + 64) >> 6;
-            // When every lane's touched samples o .. o + kmax lie inside the record (the usual
-            // case), the rows go out without a per-sample range test: one 64-bit row address
-            // per sensor, and the atomics skip the zero samples.
-            const bool inside = __all(kmax < 0 || (o >= 0 && o + kmax < p.T));
-            const uintptr_t rowp = reinterpret_cast<uintptr_t>(p.signals) +
-                                   (uintptr_t)(row_off + (int64_t)o) * sizeof(float);
-            uint32_t d1 = 0u, d0 = 0u;                   // running sums of the second differences
-            for (int q = 0; q < nblk; ++q) {
-                float* const blk = tw + q * 64 * 64;
-                float* const mat = blk - 64;
-                float col[64];
-                wave_lds_sync();
-                if (qmode) {
-                    const uint32_t* const blku = twu + q * 64 * 64;
-#pragma unroll
-                    for (int k = 0; k < 64; ++k) {
-                        d1 += blku[k * 64 + lane];
-                        d0 += d1;
-                        col[k] = (float)(int32_t)d0 * qeps;
+                sum = s_box[0][6];
+    #pragma unroll
+                for (int w = 1; w < NW; ++w) {
+    #pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = fminf(lo[a], s_box[w][a]);
+                        hi[a] = fmaxf(hi[a], s_box[w][3 + a]);
                     }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 64; ++k) col[k] = blk[k * 64 + lane];
+                    sum += s_box[w][6];
                 }
-                wave_lds_sync();
-#pragma unroll
-                for (int k = 0; k < 64; ++k) mat[lane * 65 + k] = col[k];
-                wave_lds_sync();
-                if (inside) {
-#pragma unroll
-                    for (int a0 = 0; a0 < 64; a0 += 8) {
-                        float v[8];                              // sample q*64 + lane of sensors a0 .. a0+7
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int a = a0 + u;
-                            const uint64_t pa =
-                                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(rowp >> 32), a) << 32) |
-                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rowp, a);
-                            if (v[u] != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(pa) + (q * 64 + lane), v[u]);
+                bool ok = true;
+                if (active) {
+                    if (!(sum < __builtin_huge_valf())) {
+                        ok = false;                          // a non-finite amplitude in the chunk
+                    } else if (sum > 0.f && lo[0] <= hi[0]) {
+                        double dmin, dmax;
+                        box_distance_range(lo, hi, sx, sy, sz, dmin, dmax);
+                        qs = (float)(1073741824.0 * dmin / (double)sum);
+                        ok = dmin > 0.25 * dmax && qs > 0.f && qs < __builtin_huge_valf();
+                        qeps = 1.f / qs;
+                    }                                        // else: every tile amplitude is zero
+                }
+                qmode = __all(ok);
+            }
+            uint32_t* const twu = reinterpret_cast<uint32_t*>(tw);
+
+            // Each lane's column covers samples o .. o + UCAP - 1 of its sensor.  The
+            // balls are taken in chunk order (spatially coherent after slingbag_order);
+            // when a window does not fit its column in some lane, the wave flushes the
+            // tile and re-centres every lane's column on that ball's window.
+            int o = -(1 << 30);          // no column yet: the first window triggers the set-up
+            int kmax = -1;               // last tile row written (wave-wide max at the flush)
+
+            // ---- flush, per touched 64-sample block q: each lane reads its column
+            // (64 samples of its sensor) into registers and writes it back as row
+            // `lane` of a 64 x 65 matrix that starts 64 floats before the block (in
+            // the previous, already flushed block, or the pad row before the tile); the
+            // row stride of 65 keeps both the row writes and the column reads of the
+            // matrix conflict-free.  Row a then holds 64 consecutive samples of sensor
+            // a, added to the global trace with one coalesced FP32 atomic per row.
+            auto flush = [&]() {
+                const int nblk = (wave_max_all(kmax) + 64) >> 6;
+                // When every lane's touched samples o .. o + kmax lie inside the record (the usual
+                // case), the rows go out without a per-sample range test: one 64-bit row address
+                // per sensor, and the atomics skip the zero samples.
+                const bool inside = __all(kmax < 0 || (o >= 0 && o + kmax < p.T));
+                const uintptr_t rowp = reinterpret_cast<uintptr_t>(p.signals) +
+                                       (uintptr_t)(row_off + (int64_t)o) * sizeof(float);
+                uint32_t d1 = 0u, d0 = 0u;                   // running sums of the second differences
+                for (int q = 0; q < nblk; ++q) {
+                    float* const blk = tw + q * 64 * 64;
+                    float* const mat = blk - 64;
+                    float col[64];
+                    wave_lds_sync();
+                    if (qmode) {
+                        const uint32_t* const blku = twu + q * 64 * 64;
+    #pragma unroll
+                        for (int k = 0; k < 64; ++k) {
+                            d1 += blku[k * 64 + lane];
+                            d0 += d1;
+                            col[k] = (float)(int32_t)d0 * qeps;
                         }
+                    } else {
+    #pragma unroll
+                        for (int k = 0; k < 64; ++k) col[k] = blk[k * 64 + lane];
                     }
-                } else {
-#pragma unroll
-                    for (int a0 = 0; a0 < 64; a0 += 8) {
-                        float v[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int a = a0 + u;
-                            const int act_a = __builtin_amdgcn_readlane((int)active, a);
-                            const int k = __builtin_amdgcn_readlane(o, a) + q * 64 + lane;
-                            const int64_t ra = ((int64_t)__builtin_amdgcn_readlane((int)(row_off >> 32), a) << 32) |
-                                               (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)row_off, a);
-                            if (v[u] != 0.f && act_a) {
-                                if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + ra + k, v[u]);
-                                else clipped = true;
+                    wave_lds_sync();
+    #pragma unroll
+                    for (int k = 0; k < 64; ++k) mat[lane * 65 + k] = col[k];
+                    wave_lds_sync();
+                    if (inside) {
+    #pragma unroll
+                        for (int a0 = 0; a0 < 64; a0 += 8) {
+                            float v[8];                              // sample q*64 + lane of sensors a0 .. a0+7
+    #pragma unroll
+                            for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
+    #pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int a = a0 + u;
+                                const uint64_t pa =
+                                    ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(rowp >> 32), a) << 32) |
+                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rowp, a);
+                                if (v[u] != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(pa) + (q * 64 + lane), v[u]);
+                            }
+                        }
+                    } else {
+    #pragma unroll
+                        for (int a0 = 0; a0 < 64; a0 += 8) {
+                            float v[8];
+    #pragma unroll
+                            for (int u = 0; u < 8; ++u) v[u] = mat[(a0 + u) * 65 + lane];
+    #pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int a = a0 + u;
+                                const int act_a = __builtin_amdgcn_readlane((int)active, a);
+                                const int k = __builtin_amdgcn_readlane(o, a) + q * 64 + lane;
+                                const int64_t ra = ((int64_t)__builtin_amdgcn_readlane((int)(row_off >> 32), a) << 32) |
+                                                   (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)row_off, a);
+                                if (v[u] != 0.f && act_a) {
+                                    if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + ra + k, v[u]);
+                                    else clipped = true;
+                                }
                             }
                         }
                     }
+                    wave_lds_sync();
+    #pragma unroll
+                    for (int k = 0; k < 64; ++k) blk[k * 64 + lane] = 0.f;
+                    mat[lane] = 0.f;
                 }
-                wave_lds_sync();
-#pragma unroll
-                for (int k = 0; k < 64; ++k) blk[k * 64 + lane] = 0.f;
-                mat[lane] = 0.f;
-            }
-            kmax = -1;
-        };
+                kmax = -1;
+            };
 
-        // pair set-up of ball i for this wave's sensors
-        auto setup = [&](const BallS& bs) {
-            FwdPair f;
-            const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
-            const bool valid = Wc != 0, too_long = Wc < 0;
-            f.W = Wc > 0 ? Wc : 5;                           // no window: zeros at the first rows
-            float ri;
-            const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
-            const bool ok = r > bs.Rd;                       // outside the uniform ball (r > 0: Gaussian)
-            const double u = fma(r, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
-            const double kl = floor(u);
-            const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
-            const bool use = active && valid && !too_long;
-            geometry |= use && !ok;
-            clipped |= (active && too_long) || (use && ok && !in_range);
-            f.in_tile = use && ok && in_range;               // the window exists (placed at apply)
-            f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
-            f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
-            f.klo = in_range ? (int)kl : 0;
-            f.rhof = bs.rhof;
-            return f;
-        };
-        auto prep = [&](int i) { return setup(sball[i]); };
-        auto apply = [&](const FwdPair& f) {
-            const bool part = f.in_tile;
-            const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
-            if (rows <= UCAP) {
-                int tl = f.klo - o;
-                if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
-                    flush();
-                    if (part) o = f.klo - ((UCAP - rows) >> 1);
-                    tl = f.klo - o;
-                }
-                // lanes without a window add zeros at the first rows
-                const int tr = part ? tl : 0;
-                add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
-                if (part) kmax = max(kmax, tl + f.W - 1);
-            } else if (part) {
-                clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
-            }
-        };
-        if (KERNEL == SB_KERNEL_UNIFORM && qmode) {
-            // Integer tile.  Per ball: place this ball's window (flushing if needed),
-            // issue the seven row reads, run the next ball's FP64 set-up while the reads
-            // are in flight, then write the seven rows.  Balls are read from LDS two
-            // ahead, so the set-up never waits for the row reads.
-            FwdPair cur = prep(0);
-            BallS bn = sball[min(1, nb - 1)];
-            for (int i = 0; i < nb; ++i) {
-                const BallS bnn = sball[min(i + 2, nb - 1)];
-                const bool part = cur.in_tile;
-                const int rows = max(cur.W, 5) + 2;           // the same in every lane
-                const bool in_lds = rows <= UCAP;
-                int tr = 0;                                   // the window's first tile row
-                if (in_lds) {
-                    // the loop's one flush site: flush and re-centre when this ball's
-                    // window leaves some lane's column
-                    int tl = cur.klo - o;
+            // pair set-up of ball i for this wave's sensors
+            auto setup = [&](const BallS& bs) {
+                FwdPair f;
+                const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
+                const bool valid = Wc != 0, too_long = Wc < 0;
+                f.W = Wc > 0 ? Wc : 5;                           // no window: zeros at the first rows
+                float ri;
+                const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
+                const bool ok = r > bs.Rd;                       // outside the uniform ball (r > 0: Gaussian)
+                const double u = fma(r, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
+                const double kl = floor(u);
+                const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
+                const bool use = active && valid && !too_long;
+                geometry |= use && !ok;
+                clipped |= (active && too_long) || (use && ok && !in_range);
+                f.in_tile = use && ok && in_range;               // the window exists (placed at apply)
+                f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
+                f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
+                f.klo = in_range ? (int)kl : 0;
+                f.rhof = bs.rhof;
+                return f;
+            };
+            auto prep = [&](int i) { return setup(sball[i]); };
+            auto apply = [&](const FwdPair& f) {
+                const bool part = f.in_tile;
+                const int rows = (KERNEL == SB_KERNEL_UNIFORM) ? max(f.W, 3) : f.W;
+                if (rows <= UCAP) {
+                    int tl = f.klo - o;
                     if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
                         flush();
-                        if (part) o = cur.klo - ((UCAP - rows) >> 1);
-                        tl = cur.klo - o;
+                        if (part) o = f.klo - ((UCAP - rows) >> 1);
+                        tl = f.klo - o;
                     }
-                    if (part) kmax = max(kmax, tl + rows - 1);
-                    tr = part ? tl : 0;
+                    // lanes without a window add zeros at the first rows
+                    const int tr = part ? tl : 0;
+                    add_window<KERNEL>(tw + tr * 64 + lane, f.W, part ? f.xg : 0.f, f.rhof, part ? f.Cg : 0.f);
+                    if (part) kmax = max(kmax, tl + f.W - 1);
+                } else if (part) {
+                    clipped |= add_window_global<KERNEL>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
                 }
-                FwdPair nxt;
-                if (cur.W >= 5 && in_lds) {
-                    // common case, one basic block: the window's values, the next ball's
-                    // set-up and the row updates interleave
-                    const D2Win dw = d2_window<true>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
-                    uint32_t* const c0 = twu + tr * 64 + lane;
-                    uint32_t* const c1 = c0 + dw.w2 * 64;
-                    const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
-                    const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
-                    nxt = setup(bn);
-                    c0[0] = o0 + dw.d[0];
-                    c0[64] = o1 + dw.d[1];
-                    c0[128] = o2 + dw.d[2];
-                    c1[0] = o3 + dw.d[3];
-                    c1[64] = o4 + dw.d[4];
-                    c1[128] = o5 + dw.d[5];
-                    c1[192] = o6 + dw.d[6];
-                } else {
+            };
+            if (KERNEL == SB_KERNEL_UNIFORM && qmode) {
+                // Integer tile.  Per ball: place this ball's window (flushing if needed),
+                // issue the seven row reads, run the next ball's FP64 set-up while the reads
+                // are in flight, then write the seven rows.  Balls are read from LDS two
+                // ahead, so the set-up never waits for the row reads.
+                FwdPair cur = prep(0);
+                BallS bn = sball[min(1, nb - 1)];
+                for (int i = 0; i < nb; ++i) {
+                    const BallS bnn = sball[min(i + 2, nb - 1)];
+                    const bool part = cur.in_tile;
+                    const int rows = max(cur.W, 5) + 2;           // the same in every lane
+                    const bool in_lds = rows <= UCAP;
+                    int tr = 0;                                   // the window's first tile row
                     if (in_lds) {
-                        const D2Win dw = d2_window<false>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
+                        // the loop's one flush site: flush and re-centre when this ball's
+                        // window leaves some lane's column
+                        int tl = cur.klo - o;
+                        if (__ballot(part && (tl < 0 || tl + rows > UCAP))) {
+                            flush();
+                            if (part) o = cur.klo - ((UCAP - rows) >> 1);
+                            tl = cur.klo - o;
+                        }
+                        if (part) kmax = max(kmax, tl + rows - 1);
+                        tr = part ? tl : 0;
+                    }
+                    FwdPair nxt;
+                    if (cur.W >= 5 && in_lds) {
+                        // common case, one basic block: the window's values, the next ball's
+                        // set-up and the row updates interleave
+                        const D2Win dw = d2_window<true>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
                         uint32_t* const c0 = twu + tr * 64 + lane;
                         uint32_t* const c1 = c0 + dw.w2 * 64;
                         const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
                         const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
+                        nxt = setup(bn);
                         c0[0] = o0 + dw.d[0];
                         c0[64] = o1 + dw.d[1];
                         c0[128] = o2 + dw.d[2];
@@ -531,25 +520,40 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                         c1[64] = o4 + dw.d[4];
                         c1[128] = o5 + dw.d[5];
                         c1[192] = o6 + dw.d[6];
-                    } else if (part) {
-                        clipped |= add_window_global<KERNEL>(out_row, cur.klo, p.T, cur.W, cur.xg, cur.rhof, cur.Cg);
+                    } else {
+                        if (in_lds) {
+                            const D2Win dw = d2_window<false>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
+                            uint32_t* const c0 = twu + tr * 64 + lane;
+                            uint32_t* const c1 = c0 + dw.w2 * 64;
+                            const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
+                            const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
+                            c0[0] = o0 + dw.d[0];
+                            c0[64] = o1 + dw.d[1];
+                            c0[128] = o2 + dw.d[2];
+                            c1[0] = o3 + dw.d[3];
+                            c1[64] = o4 + dw.d[4];
+                            c1[128] = o5 + dw.d[5];
+                            c1[192] = o6 + dw.d[6];
+                        } else if (part) {
+                            clipped |= add_window_global<KERNEL>(out_row, cur.klo, p.T, cur.W, cur.xg, cur.rhof, cur.Cg);
+                        }
+                        nxt = setup(bn);
                     }
-                    nxt = setup(bn);
+                    cur = nxt;
+                    bn = bnn;
                 }
-                cur = nxt;
-                bn = bnn;
+            } else {
+                // FP32 tile; software pipeline: the set-up of ball i+1 overlaps the tile
+                // update of ball i
+                FwdPair cur = prep(0);
+                for (int i = 0; i < nb; ++i) {
+                    const FwdPair nxt = prep(min(i + 1, nb - 1));
+                    apply(cur);
+                    cur = nxt;
+                }
             }
-        } else {
-            // FP32 tile; software pipeline: the set-up of ball i+1 overlaps the tile
-            // update of ball i
-            FwdPair cur = prep(0);
-            for (int i = 0; i < nb; ++i) {
-                const FwdPair nxt = prep(min(i + 1, nb - 1));
-                apply(cur);
-                cur = nxt;
-            }
+            flush();
         }
-        flush();
     }
     if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
     if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);

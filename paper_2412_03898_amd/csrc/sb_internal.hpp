@@ -40,6 +40,8 @@ struct OpParams {
     int32_t S, T;
     int32_t basis, pos_mode, n_terms, M;
     int32_t n_sblocks;       // forward: sensor blocks per (frame, chunk); adjoint: sensor splits
+    int32_t sb_per_item;     // forward: sensor blocks per work item (the chunk is staged once for them)
+    int32_t n_sitems;        // forward: items per (frame, chunk) = ceil(n_sblocks / sb_per_item)
     int32_t s_per_split;     // adjoint: sensors per split
     int32_t n_scenes;
     Scene scenes[SB_MAX_SCENES];
@@ -58,8 +60,8 @@ struct BallF {
 // Gaussian-ball traces are cut where |r - c t| > kGaussCut * a (+ half a sample).
 constexpr float kGaussCut = 6.0f;
 
-// Work item -> (scene, local frame, group, sensor block).  Items of one scene are
-// ordered frame-major, then group, then sensor block.
+// Work item -> (scene, local frame, group, first sensor block).  Items of one scene
+// are ordered frame-major, then group, then sensor block.
 struct Item {
     int scene, frame, group, sblock;
 };
@@ -71,8 +73,8 @@ __device__ inline Item decode_item(const OpParams& p, int64_t item) {
     int64_t local = item - sc.item0;
     Item it;
     it.scene = i;
-    it.sblock = (int)(local % p.n_sblocks);
-    int64_t q = local / p.n_sblocks;
+    it.sblock = (int)(local % p.n_sitems) * p.sb_per_item;     // first sensor block of the item
+    int64_t q = local / p.n_sitems;
     it.group = (int)(q % sc.n_groups);
     it.frame = (int)(q / sc.n_groups);
     return it;

@@ -1,8 +1,9 @@
 // Forward operator: per (ball, sensor, frame) scatter of a short sampled trace.
 //
-// Work item = (scene, frame, chunk of G consecutive balls, block of 64*NW
-// sensors).  The block stages the chunk's deformed balls (Eq. 1, recomputed
-// here) in LDS.  Each wave owns 64 sensors, one per lane, and each lane owns
+// Work item = (scene, frame, chunk of G consecutive balls, one or more blocks
+// of 64*NW sensors).  The block stages the chunk's deformed balls (Eq. 1,
+// recomputed here) in LDS once, then takes its sensor blocks one after the
+// other.  Each wave owns 64 sensors, one per lane, and each lane owns
 // one column of the wave's LDS trace tile T[UCAP][64] (column c lives in bank
 // c mod 32: no conflicts while lanes add their windows at different samples).
 // The column of a lane covers UCAP consecutive samples of its sensor from an
@@ -16,7 +17,9 @@
 // transposes each touched 64-sample block through LDS so that one row holds 64
 // consecutive samples of one sensor, and adds it to the global trace with one
 // coalesced FP32 atomic per row.  Windows longer than the tile go to global
-// memory directly.
+// memory directly.  For the uniform sphere the tile normally holds the traces'
+// second differences as exact integers (see d2_window), so that a window costs
+// seven tile updates whatever its length; the flush integrates them back.
 //
 // Trace of one ball in sample units (tau = (r - c t0)/delta, rho = R_f/delta):
 // with boundaries x_m = tau - k_lo + 1/2 - m, m = 0..W, between samples,

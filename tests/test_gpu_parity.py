@@ -455,3 +455,32 @@ def test_every_knob_setting_matches_oracle(col, occ):
     finally:
         for k, v in saved.items():
             binding.tune(k, v)
+
+
+@pytest.mark.parametrize("col", [64, 128])
+def test_windows_longer_than_the_column(col):
+    """Uniform spheres whose windows need more tile rows than the column holds (W from 55
+    to 150 samples, R up to 2.8 mm) mixed with ordinary ones: the long windows go to the
+    global trace directly, the chunk's integer-tile bound leaves them out."""
+    from paper_2412_03898_amd import binding
+    wl = tiny_scene(n_balls=400, n_sensors=70, seed=88)
+    b = wl.balls.copy()
+    rng = np.random.default_rng(88)
+    delta = wl.c / wl.fs
+    W = np.where(rng.uniform(size=b.shape[1]) < 0.3, rng.integers(55, 151, size=b.shape[1]),
+                 rng.integers(7, 20, size=b.shape[1]))
+    b[3] = ((W - 2 + rng.uniform(0.05, 0.95, size=W.size)) * delta / 2).astype(np.float32)
+    k0 = synth.record_start(0.060, 0.010, 3.0e-3, 0.5e-3)
+    n = synth.record_length_needed(0.060, 0.010, 3.0e-3, 0.5e-3, k0)
+    wl = _morton(with_(wl, balls=b, t0=k0 / wl.fs, n_samples=n))
+    saved = binding.tune_get(binding.SB_TUNE_FWD_COLUMN)
+    try:
+        binding.tune(binding.SB_TUNE_FWD_COLUMN, col)
+        y, flags = gpu_forward(wl)
+    finally:
+        binding.tune(binding.SB_TUNE_FWD_COLUMN, saved)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"windows longer than the column ({col}): rel-L2 {err:.3e} flags={flags}")
+    assert flags == 0
+    assert err <= SIG_TOL

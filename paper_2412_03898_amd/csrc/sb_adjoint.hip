@@ -218,17 +218,39 @@ __global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
                         // every boundary m = 0..W (r_{-1} = r_W = 0)
                         const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale
                         float rp = 0.f;
-                        for (int m = 0; m <= W; ++m) {
-                            const int k = klo + m;
-                            float rm = 0.f;
-                            if (m < W) rm = in_row ? row[tl + m] : ((k >= 0 && k < p.T) ? rres[k] : 0.f);
-                            const float dr = rm - rp;
-                            rp = rm;
-                            const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
-                            A += e;
-                            Bs = fmaf(x, e, Bs);
-                            Cs = fmaf(x * x, e, Cs);
-                            x -= 1.f;
+                        if (in_row) {
+                            // eight boundaries per batch, their samples read together (indices
+                            // clamped into the window; boundaries past W contribute nothing)
+                            const float* rw = row + tl;          // samples 0..W-1 lie in the row
+                            for (int m0 = 0; m0 <= W; m0 += 8) {
+                                float v[8];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) v[u] = rw[min(m0 + u, W - 1)];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    const int m = m0 + u;
+                                    const float rm = (m < W) ? v[u] : 0.f;
+                                    const float dr = (m <= W) ? rm - rp : 0.f;
+                                    rp = rm;
+                                    const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
+                                    A += e;
+                                    Bs = fmaf(x, e, Bs);
+                                    Cs = fmaf(x * x, e, Cs);
+                                    x -= 1.f;
+                                }
+                            }
+                        } else {
+                            for (int m = 0; m <= W; ++m) {
+                                const int k = klo + m;
+                                const float rm = (m < W && k >= 0 && k < p.T) ? rres[k] : 0.f;
+                                const float dr = rm - rp;
+                                rp = rm;
+                                const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
+                                A += e;
+                                Bs = fmaf(x, e, Bs);
+                                Cs = fmaf(x * x, e, Cs);
+                                x -= 1.f;
+                            }
                         }
                     }
                 }

@@ -99,9 +99,26 @@ __device__ inline void add_window(float* c, int W, float x0, float rho, float C)
             if (n & 1) add_ramp<1>(cp, yb, m2c);
         }
     } else {
+        // Gaussian ball: eight samples per batch, all eight rows read before any is
+        // written back (one LDS wait per batch instead of one per sample)
         const float ce = -1.f / (2.f * rho * rho);
         float Ep = __expf(x0 * x0 * ce), x = x0;
-        for (int j = 0; j < W; ++j) {
+        int j = 0;
+        for (; j + 8 <= W; j += 8) {
+            float o[8], v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o[u] = c[(j + u) * 64];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                x -= 1.f;
+                const float E = __expf(x * x * ce);
+                v[u] = C * (E - Ep);
+                Ep = E;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) c[(j + u) * 64] = o[u] + v[u];
+        }
+        for (; j < W; ++j) {
             x -= 1.f;
             const float E = __expf(x * x * ce);
             c[j * 64] += C * (E - Ep);

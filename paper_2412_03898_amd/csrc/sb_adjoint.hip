@@ -1,6 +1,10 @@
 // Adjoint: gradient of 1/2 |y - d|^2 with respect to every ball attribute and
 // deformation coefficient, given the residual y - d.
 //
+// Two kernels.  The uniform sphere's (adjoint_uniform_kernel, further below) sums
+// each window in closed form from prefix sums of a staged residual row.  The
+// Gaussian ball's (adjoint_gauss_kernel) gathers every window boundary:
+//
 // Work item = (scene, chunk of 256 consecutive balls, split of the sensors).
 // A block of four waves takes the chunk and ranks its balls by size, so that
 // each wave holds 64 balls of similar size (similar window lengths keep the
@@ -14,14 +18,9 @@
 // reductions and no atomics until the chain rule at the end of the item.
 //
 // Sums by parts over the window boundaries x_m (residual differences
-// dr_m = r_m - r_{m-1}, r_{-1} = r_W = 0).  Uniform sphere: boundaries m = 1..m_hi
-// lie strictly inside (-rho, rho) (decided in FP64); the clamped ones
-// telescope, so with
-//   S_w = sum_in x_m^2 dr_m - rho^2 S_r,  S_t = sum_in x_m dr_m,  S_r = r_{m_hi} - r_0
-// and C = P_f delta / (4r):  G_v = C S_w,  G_tau = 2 C S_t,  G_rho = -2 rho C S_r.
-// Gaussian ball: all boundaries, E_m = exp(-x_m^2 / (2 rho^2)), K = P_f rho^2 delta/(2r),
-// S_n = sum x_m^n E_m dr_m:  G_v = -K S0,  G_tau = K/rho^2 S1,
-// G_rho = -2K/rho S0 - K/rho^3 S2.
+// dr_m = r_m - r_{m-1}, r_{-1} = r_W = 0), E_m = exp(-x_m^2 / (2 rho^2)),
+// K = P_f rho^2 delta/(2r), S_n = sum x_m^n E_m dr_m:  G_v = -K S0,
+// G_tau = K/rho^2 S1, G_rho = -2K/rho S0 - K/rho^3 S2.
 // Then dL/dr = G_tau/delta - G_v/r, dL/dR_f = G_rho/delta, dL/dP_f = G_v/P_f and
 // dL/dx_f = dL/dr (x_f - s)/r; the chain rule through Eq. 1 (and Eq. 2 or the
 // Fourier series) gives the parameter gradients.
@@ -33,8 +32,8 @@ namespace sb {
 constexpr int kAdjChunk = 256;   // balls per block item (4 waves x 64 lanes)
 constexpr int kAdjMaxSplit = 256;   // sensors per item at most
 
-template <int UROW, int KERNEL, int MREG, int OCC>
-__global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
+template <int UROW, int MREG, int OCC>
+__global__ __launch_bounds__(256, OCC) void adjoint_gauss_kernel(OpParams p) {
     static_assert(UROW % 64 == 0, "row length must be a multiple of 64");
     constexpr int NQ = UROW / 64;
     __shared__ float rowbuf[4][UROW];
@@ -111,7 +110,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
             for (int a = 0; a < 3; ++a) { lo[a] = wave_min(lo[a]); hi[a] = wave_max(hi[a]); }
             rmax = wave_max(rmax);
             if (!(lo[0] <= hi[0])) continue;           // no live ball in this wave
-            const double hmax = (KERNEL == SB_KERNEL_UNIFORM) ? (double)rmax : (double)kGaussCut * rmax;
+            const double hmax = (double)kGaussCut * rmax;
             // row origins of all sensors of the split, one sensor per lane: every
             // window of the wave starts at or after o + 1
             wave_lds_sync();
@@ -126,13 +125,11 @@ __global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
 
             // per-ball constants of this frame
             const float rho = live ? bl.rhof : 0.f;
-            const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
+            const double h = (double)kGaussCut * bl.rho;
             const double h_half = h - 0.5;
-            const double r_in = bl.rho * (double)delta;       // sensor must be farther than this
+            const double r_in = 0.0;                           // the sensor must not sit at the centre
             const int W = live ? (int)(2.0 * h) + 2 : 0;
             const bool w_ok = live && h < 1.0e6;
-            // wave-uniform trip count of the gather loop
-            const int n_it = wave_max_i(KERNEL == SB_KERNEL_UNIFORM ? W - 1 : W + 1);
             const float* res_frame = p.residual + (int64_t)gf * p.S * p.T;
             float g5[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
 
@@ -175,46 +172,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
                 float A = 0.f, Bs = 0.f, Cs = 0.f;
                 if (use) {
                     float x = (float)a0d;
-                    if (KERNEL == SB_KERNEL_UNIFORM) {
-                        // inside boundaries m = 1..m_hi (m_hi decided in FP64); the loop runs a
-                        // wave-uniform count, later boundaries are masked (dr = 0)
-                        const int m_hi = (int)ceil(a0d + bl.rho) - 1;
-                        float r0, rp, sw = 0.f, st = 0.f;
-                        if (in_row) {
-                            const float* rw = row + tl;          // samples 0..W-1 lie in the row
-                            r0 = rw[0];
-                            rp = r0;
-                            for (int m = 1; m <= n_it; m += 4) {
-                                float v[4];
-#pragma unroll
-                                for (int u = 0; u < 4; ++u) v[u] = rw[min(m + u, W - 1)];
-#pragma unroll
-                                for (int u = 0; u < 4; ++u) {
-                                    x -= 1.f;
-                                    const float rm = (m + u <= m_hi) ? v[u] : rp;
-                                    const float dr = rm - rp;
-                                    rp = rm;
-                                    sw = fmaf(x * x, dr, sw);
-                                    st = fmaf(x, dr, st);
-                                }
-                            }
-                        } else {
-                            r0 = (klo >= 0 && klo < p.T) ? rres[klo] : 0.f;
-                            rp = r0;
-                            for (int m = 1; m <= m_hi; ++m) {
-                                x -= 1.f;
-                                const int k = klo + m;
-                                const float rm = (k >= 0 && k < p.T) ? rres[k] : 0.f;
-                                const float dr = rm - rp;
-                                rp = rm;
-                                sw = fmaf(x * x, dr, sw);
-                                st = fmaf(x, dr, st);
-                            }
-                        }
-                        Cs = rp - r0;
-                        A = fmaf(-rho * rho, Cs, sw);
-                        Bs = st;
-                    } else {
+                    {
                         // every boundary m = 0..W (r_{-1} = r_W = 0)
                         const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale
                         float rp = 0.f;
@@ -258,13 +216,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_kernel(OpParams p) {
                     const float rf = (float)r;
                     const float inv_r = __builtin_amdgcn_rcpf(rf);
                     float dLdr, dLdR, dLdP;
-                    if (KERNEL == SB_KERNEL_UNIFORM) {
-                        const float Cr = delta * 0.25f * inv_r;   // C / P_f
-                        const float C = bl.amp * Cr;
-                        dLdr = 2.f * C * Bs * inv_delta_f - C * A * inv_r;
-                        dLdR = -2.f * rho * C * Cs * inv_delta_f;
-                        dLdP = Cr * A;
-                    } else {
+                    {
                         const float Kr = rho * rho * delta * 0.5f * inv_r;   // K / P_f
                         const float K = bl.amp * Kr;
                         dLdr = K / (rho * rho) * Bs * inv_delta_f + K * A * inv_r;
@@ -631,19 +583,19 @@ static hipError_t launch_adj_um(const OpParams& p, hipStream_t st) {
     return reg ? launch_adj_u<4, OCC>(p, st) : launch_adj_u<0, OCC>(p, st);
 }
 
-template <int UROW, int KERNEL, int MREG, int OCC>
+template <int UROW, int MREG, int OCC>
 static hipError_t launch_adj_t(const OpParams& p, hipStream_t st) {
     int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((adjoint_kernel<UROW, KERNEL, MREG, OCC>), dim3((unsigned)grid), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((adjoint_gauss_kernel<UROW, MREG, OCC>), dim3((unsigned)grid), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
-template <int UROW, int KERNEL, int OCC>
+template <int UROW, int OCC>
 static hipError_t launch_adj_m(const OpParams& p, hipStream_t st) {
     // register accumulators for the Fourier coefficients when they fit (K <= 2)
     const bool reg = p.basis == SB_BASIS_FOURIER && p.M == 4;
-    return reg ? launch_adj_t<UROW, KERNEL, 4, OCC>(p, st) : launch_adj_t<UROW, KERNEL, 0, OCC>(p, st);
+    return reg ? launch_adj_t<UROW, 4, OCC>(p, st) : launch_adj_t<UROW, 0, OCC>(p, st);
 }
 
 // tc.ucap: residual row length; tc.nw: blocks per CU requested from the compiler (occupancy)
@@ -653,7 +605,7 @@ hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipS
         if (tc.nw == 3) return launch_adj_um<3>(p, st);
         if (tc.nw == 4) return launch_adj_um<4>(p, st);
     }
-    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 192 && tc.nw == 2) return launch_adj_m<192, 1, 2>(p, st);
+    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 192 && tc.nw == 2) return launch_adj_m<192, 2>(p, st);
     return hipErrorInvalidValue;
 }
 

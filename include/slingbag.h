@@ -208,6 +208,9 @@ int slingbag_plan_destroy(sb_plan* plan);
  * candidates on the caller's own shapes and sets the fastest.
  *   SB_TUNE_FWD_COLUMN     forward LDS column length: 64 or 128 samples (uniform sphere);
  *                          default 64
+ *   SB_TUNE_FWD_GAUSS_COLUMN  forward LDS column length for the Gaussian ball: 128 samples
+ *                          (blocks of 4 waves) or 256 (blocks of 2 waves, for windows that
+ *                          nearly fill 128 rows); default 256
  *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4;
  *                          default 4
  *   SB_TUNE_ADJ_ITEMS      adjoint work items the sensor split aims for: 1 .. 2^22;
@@ -216,17 +219,20 @@ int slingbag_plan_destroy(sb_plan* plan);
 #define SB_TUNE_FWD_COLUMN     1
 #define SB_TUNE_ADJ_OCCUPANCY  2
 #define SB_TUNE_ADJ_ITEMS      3
+#define SB_TUNE_FWD_GAUSS_COLUMN 4
 int slingbag_tune(int key, int value);
 int slingbag_tune_get(int key, int* value);
 
-/* Autotuner: runs the forward with every forward column length and the
- * adjoint with every (occupancy, item count) candidate on the caller's own
+/* Autotuner: runs the forward with every column length of the problem's kernel
+ * (SB_TUNE_FWD_COLUMN for the uniform sphere, SB_TUNE_FWD_GAUSS_COLUMN for the
+ * Gaussian ball) and the adjoint with every (occupancy, item count) candidate on the caller's own
  * problem (the arguments of slingbag_forward / slingbag_adjoint; signals,
  * grad_balls and grad_deform are overwritten, the forward output serves as
  * the adjoint's residual), times each with HIP events on `stream` (one
  * warm-up and two timed runs), keeps the fastest setting of every knob and
- * writes it to choice[3] (HOST: forward column, adjoint occupancy, adjoint
- * items).  Synchronises the stream.  Not for use under graph capture. */
+ * writes it to choice[3] (HOST: forward column of the problem's kernel, adjoint
+ * occupancy, adjoint items).  Synchronises the stream.  Not for use under graph
+ * capture. */
 int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* balls,
                       const float* deform, const float* frame_t, const float* sensors, float* signals,
                       float* grad_balls, float* grad_deform, int32_t* choice, void* stream);

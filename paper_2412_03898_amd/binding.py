@@ -234,7 +234,7 @@ def check(stream: int = 0) -> int:
     return int(flags.value)
 
 
-SB_TUNE_FWD_COLUMN, SB_TUNE_ADJ_OCCUPANCY, SB_TUNE_ADJ_ITEMS = 1, 2, 3
+SB_TUNE_FWD_COLUMN, SB_TUNE_ADJ_OCCUPANCY, SB_TUNE_ADJ_ITEMS, SB_TUNE_FWD_GAUSS_COLUMN = 1, 2, 3, 4
 
 
 def tune(key: int, value: int):

@@ -605,7 +605,7 @@ hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipS
         if (tc.nw == 3) return launch_adj_um<3>(p, st);
         if (tc.nw == 4) return launch_adj_um<4>(p, st);
     }
-    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 192 && tc.nw == 2) return launch_adj_m<192, 2>(p, st);
+    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 384 && tc.nw == 2) return launch_adj_m<384, 2>(p, st);
     return hipErrorInvalidValue;
 }
 

@@ -127,7 +127,8 @@ static int validate_batch(const sb_batch* batch, Shape& sh) {
 // and adjoint item count.  They change speed, not results (beyond the order of
 // floating-point atomics).
 struct Tuning {
-    int fwd_ucap = 64;         // 64 or 128 samples per LDS column
+    int fwd_ucap = 64;         // 64 or 128 samples per LDS column (uniform sphere)
+    int fwd_gauss_ucap = 256;  // 128 (4-wave blocks) or 256 (2-wave blocks): Gaussian ball
     int adj_occ = 4;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
     int adj_items = 8192;      // adjoint items the sensor split aims for
 };
@@ -135,9 +136,10 @@ static Tuning g_tune;
 
 static TileCfg pick_forward_tiles(int kernel) {
     TileCfg tc;
-    tc.nw = 4;
-    tc.g = 256;
-    tc.ucap = kernel == SB_KERNEL_UNIFORM ? g_tune.fwd_ucap : 128;
+    const bool long_col = kernel != SB_KERNEL_UNIFORM && g_tune.fwd_gauss_ucap == 256;
+    tc.nw = long_col ? 2 : 4;
+    tc.g = 64 * tc.nw;
+    tc.ucap = kernel == SB_KERNEL_UNIFORM ? g_tune.fwd_ucap : g_tune.fwd_gauss_ucap;
     return tc;
 }
 
@@ -145,7 +147,7 @@ static TileCfg pick_adjoint_tiles(int kernel) {
     TileCfg tc;
     tc.nw = kernel == SB_KERNEL_UNIFORM ? g_tune.adj_occ : 2;
     tc.g = 256;
-    tc.ucap = kernel == SB_KERNEL_UNIFORM ? 128 : 192;
+    tc.ucap = kernel == SB_KERNEL_UNIFORM ? 128 : 384;
     return tc;
 }
 
@@ -517,6 +519,11 @@ int slingbag_tune(int key, int value) {
             if (value != 64 && value != 128) return fail(SB_ERR_INVALID_ARG, "forward column must be 64 or 128");
             g_tune.fwd_ucap = value;
             return SB_OK;
+        case SB_TUNE_FWD_GAUSS_COLUMN:
+            if (value != 128 && value != 256)
+                return fail(SB_ERR_INVALID_ARG, "Gaussian forward column must be 128 or 256");
+            g_tune.fwd_gauss_ucap = value;
+            return SB_OK;
         case SB_TUNE_ADJ_OCCUPANCY:
             if (value < 2 || value > 4) return fail(SB_ERR_INVALID_ARG, "adjoint occupancy must be 2..4");
             g_tune.adj_occ = value;
@@ -542,15 +549,18 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
     const int reps = 2;
     const Tuning saved = g_tune;
     float best = 3.0e38f, ms = 0.f;
-    int best_col = g_tune.fwd_ucap;
-    for (int col : {64, 128}) {
-        if (cfg->kernel != SB_KERNEL_UNIFORM && col != 128) continue;
-        g_tune.fwd_ucap = col;
+    // the column knob of the problem's kernel: 64 / 128 (uniform sphere), 128 / 256 (Gaussian ball)
+    const bool uni = cfg->kernel == SB_KERNEL_UNIFORM;
+    int& col_knob = uni ? g_tune.fwd_ucap : g_tune.fwd_gauss_ucap;
+    int best_col = col_knob;
+    for (int col : {64, 128, 256}) {
+        if (uni ? col == 256 : col == 64) continue;
+        col_knob = col;
         st = time_ms(s, reps, [&] { return slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream); }, &ms);
         if (st) { g_tune = saved; return st; }
         if (ms < best) { best = ms; best_col = col; }
     }
-    g_tune.fwd_ucap = best_col;
+    col_knob = best_col;
     // the forward output serves as a finite residual for timing the adjoint
     st = slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream);
     if (st) { g_tune = saved; return st; }
@@ -580,6 +590,7 @@ int slingbag_tune_get(int key, int* value) {
     std::lock_guard<std::mutex> lk(g_mu);
     switch (key) {
         case SB_TUNE_FWD_COLUMN: *value = g_tune.fwd_ucap; return SB_OK;
+        case SB_TUNE_FWD_GAUSS_COLUMN: *value = g_tune.fwd_gauss_ucap; return SB_OK;
         case SB_TUNE_ADJ_OCCUPANCY: *value = g_tune.adj_occ; return SB_OK;
         case SB_TUNE_ADJ_ITEMS: *value = g_tune.adj_items; return SB_OK;
         default: return fail(SB_ERR_INVALID_ARG, "unknown tuning key %d", key);

@@ -29,9 +29,11 @@ def shape_key(pb: Problem) -> str:
             f"B{int(round(math.log2(b)))}-F{int(round(math.log2(f)))}-sc{len(pb.ball_offset) - 1}")
 
 
-def apply(choice):
+def apply(choice, kernel: int = 0):
+    """Set the knobs of a choice; the column goes to the knob of `kernel` (0 uniform
+    sphere, 1 Gaussian ball)."""
     col, occ, items = choice
-    binding.tune(binding.SB_TUNE_FWD_COLUMN, col)
+    binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN if kernel == 1 else binding.SB_TUNE_FWD_COLUMN, col)
     binding.tune(binding.SB_TUNE_ADJ_OCCUPANCY, occ)
     binding.tune(binding.SB_TUNE_ADJ_ITEMS, items)
 
@@ -49,7 +51,7 @@ def autotune(pb: Problem, balls, deform, frame_t, sensors, cache: str | None = D
             table = {}
     if not force and key in table:
         choice = tuple(int(v) for v in table[key])
-        apply(choice)
+        apply(choice, pb.cfg.kernel)
         return choice
     B, F = pb.n_balls, pb.n_frames
     S, T, M = pb.cfg.n_sensors, pb.cfg.n_samples, pb.n_coef

@@ -127,12 +127,15 @@ def test_tuning_knobs_validate_and_round_trip():
     assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 96) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_tune(binding.SB_TUNE_ADJ_OCCUPANCY, 5) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_tune(binding.SB_TUNE_ADJ_ITEMS, 0) == binding.SB_ERR_INVALID_ARG
-    saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
+    assert lib.slingbag_tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, 64) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 256) == binding.SB_ERR_INVALID_ARG
+    saved = {k: binding.tune_get(k) for k in (1, 2, 3, 4)}
     try:
         binding.tune(binding.SB_TUNE_FWD_COLUMN, 64)
         binding.tune(binding.SB_TUNE_ADJ_OCCUPANCY, 3)
         binding.tune(binding.SB_TUNE_ADJ_ITEMS, 1234)
-        assert (binding.tune_get(1), binding.tune_get(2), binding.tune_get(3)) == (64, 3, 1234)
+        binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, 128)
+        assert tuple(binding.tune_get(k) for k in (1, 2, 3, 4)) == (64, 3, 1234, 128)
     finally:
         for k, v in saved.items():
             binding.tune(k, v)

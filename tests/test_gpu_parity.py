@@ -421,7 +421,7 @@ def test_autotune_then_parity():
     from paper_2412_03898_amd import binding, ops, tune
     wl = synth.apply_order(synth.workload_vessel_4d(n_balls=3000, n_sensors=70, n_frames=4))
     pb, balls, deform, ft, sens = ops.to_device(wl)
-    saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
+    saved = {k: binding.tune_get(k) for k in (1, 2, 3, 4)}
     try:
         choice = tune.autotune(pb, balls, deform, ft, sens, cache=None)
         assert choice[0] in (64, 128) and choice[1] in (2, 3, 4) and choice[2] in (2048, 4096, 8192, 16384)
@@ -442,7 +442,7 @@ def test_every_knob_setting_matches_oracle(col, occ):
     """Every kernel instance the tuner can pick gives oracle-parity results."""
     from paper_2412_03898_amd import binding
     wl = synth.apply_order(synth.workload_vessel_static(n_balls=6000, n_sensors=130, n_samples=4096))
-    saved = {k: binding.tune_get(k) for k in (1, 2, 3)}
+    saved = {k: binding.tune_get(k) for k in (1, 2, 3, 4)}
     try:
         binding.tune(binding.SB_TUNE_FWD_COLUMN, col)
         binding.tune(binding.SB_TUNE_ADJ_OCCUPANCY, occ)
@@ -482,5 +482,33 @@ def test_windows_longer_than_the_column(col):
     ref = oracle.forward(wl)
     err = rel_l2(y, ref)
     _say(f"windows longer than the column ({col}): rel-L2 {err:.3e} flags={flags}")
+    assert flags == 0
+    assert err <= SIG_TOL
+
+
+@pytest.mark.parametrize("col", [128, 256])
+def test_gaussian_ball_both_columns(col):
+    """Gaussian balls (Fourier 4D, windows of 20 to 125 samples) at both column lengths
+    of their forward: 128 rows in blocks of four waves, 256 rows in blocks of two."""
+    from paper_2412_03898_amd import binding
+    wl = tiny_scene(n_balls=600, n_sensors=140, n_frames=2, kernel=1, basis=1, seed=89)
+    b = wl.balls.copy()
+    rng = np.random.default_rng(89)
+    b[3] = rng.uniform(0.05e-3, 0.35e-3, size=b.shape[1]).astype(np.float32)   # 6 sigma: up to 125 samples
+    k0 = synth.record_start(0.060, 0.010, 0.35e-3 * 12, 0.5e-3)
+    n = synth.record_length_needed(0.060, 0.010, 0.35e-3 * 12, 0.5e-3, k0)
+    wl = with_(wl, balls=b, t0=k0 / wl.fs, n_samples=n)
+    order = synth.morton_order(wl.balls)
+    wl = with_(wl, balls=np.ascontiguousarray(wl.balls[:, order]),
+               deform=np.ascontiguousarray(wl.deform[:, :, order]))
+    saved = binding.tune_get(binding.SB_TUNE_FWD_GAUSS_COLUMN)
+    try:
+        binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, col)
+        y, flags = gpu_forward(wl)
+    finally:
+        binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, saved)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"gaussian column {col}: forward rel-L2 {err:.3e} flags={flags}")
     assert flags == 0
     assert err <= SIG_TOL

@@ -121,7 +121,12 @@ typedef struct sb_batch {
  * attributes, Eq. 1-2).  Writes signals[f][s][k] = sum over the balls of f's
  * scene of the sampled trace of that ball at sensor s (every entry is
  * overwritten; frames of empty scenes become zero).  deform may be NULL only
- * for SB_BASIS_STATIC.  Scratch: none beyond a per-device flag word. */
+ * for SB_BASIS_STATIC.  Scratch: none beyond a per-device flag word.
+ * Precision: FP64 geometry and FP32 samples; for the uniform sphere the
+ * per-chunk accumulation normally runs in integers at 2^-30 of the chunk's
+ * amplitude bound (about 1e-6 relative L2 against an FP64 evaluation), so the
+ * result depends at that level on which balls share a chunk of 256 (ball
+ * order) and on the FP32 atomic order. */
 int slingbag_forward(const sb_config* cfg, const sb_batch* batch,
                      const float* balls, const float* deform, const float* frame_t,
                      const float* sensors, float* signals, void* stream);
@@ -203,8 +208,9 @@ int slingbag_plan_run(sb_plan* plan, void* stream);
 int slingbag_plan_destroy(sb_plan* plan);
 
 /* Tuning knobs, read by every later call on any device (process-wide).  They
- * change speed only; results differ at most by the order of FP32 atomic
- * additions.  The autotuner (python: paper_2412_03898_amd.tune) times the
+ * change speed only; results differ at most by rounding (the order of FP32
+ * atomic additions, and the uniform sphere's integer accumulation scale when
+ * the column length changes which windows stay in LDS).  The autotuner (python: paper_2412_03898_amd.tune) times the
  * candidates on the caller's own shapes and sets the fastest.
  *   SB_TUNE_FWD_COLUMN     forward LDS column length: 64 or 128 samples (uniform sphere);
  *                          default 64

@@ -595,7 +595,6 @@ hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipS
     if (kernel == SB_KERNEL_UNIFORM) {
         if (tc.nw == 4 && tc.g == 256 && tc.ucap == 128) return launch_fwd_t<4, 256, 128, 0>(p, st);
         if (tc.nw == 4 && tc.g == 256 && tc.ucap == 64) return launch_fwd_t<4, 256, 64, 0>(p, st);
-        if (tc.nw == 2 && tc.g == 128 && tc.ucap == 128) return launch_fwd_t<2, 128, 128, 0>(p, st);
     } else {
         if (tc.nw == 4 && tc.g == 256 && tc.ucap == 128) return launch_fwd_t<4, 256, 128, 1>(p, st);
         if (tc.nw == 2 && tc.g == 128 && tc.ucap == 256) return launch_fwd_t<2, 128, 256, 1>(p, st);

@@ -407,7 +407,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
             // per-ball constants of this frame
             const float rho = live ? bl.rhof : 0.f;
             const double rhod = live ? bl.rho : 0.0;
-            const double h_half = rhod - 0.5;
+            const double c1 = p.t0fs + (rhod - 0.5);          // window start: floor(r / delta - c1)
             const double r_in = rhod * (double)delta;          // sensor must be farther than this
             const bool w_ok = live && rhod < 1.0e6;
             const int W = w_ok ? (int)(2.0 * rhod) + 2 : 0;
@@ -437,9 +437,9 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                     const double dz = bl.z - s_sz[j];
                     float inv_r;
                     const double r = dist64(dx, dy, dz, inv_r);
-                    const double tau = fma(r, p.inv_delta, -p.t0fs);
-                    const double kl = floor(tau - h_half);
-                    const double a0d = tau - kl + 0.5;
+                    const double uw = fma(r, p.inv_delta, -c1);    // tau - rho + 1/2
+                    const double kl = floor(uw);
+                    const double a0d = (uw - kl) + rhod;             // x_0 = tau - k_lo + 1/2
                     const bool geo = w_ok && r > r_in;
                     geometry |= w_ok && !geo;
                     const bool use = geo && fabs(kl) < 5.0e8;
@@ -448,21 +448,26 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                     const bool in_row = use && tl >= 0 && tl + W <= kPfxRow;
                     // inside boundaries m = 1..M (M decided in FP64)
                     const int M = use ? (int)ceil(a0d + rhod) - 1 : 0;
-                    // prefix form (lanes outside the row read row entry 0 and discard it)
+                    // prefix form (lanes outside the row read row entry 0 and discard it);
+                    // byte offsets from the slot base keep the address arithmetic to shifts
                     const int t0 = in_row ? tl : 0, iM = in_row ? tl + M : 0;
-                    const float r0 = sl.rowf[t0], rM = sl.rowf[iM];
-                    const double2 pa = sl.pfx[t0 + 1], pb = sl.pfx[iM];
+                    const char* const slb = reinterpret_cast<const char*>(&sl);
+                    constexpr int kRowOff = (int)offsetof(PfxSlot, rowf);
+                    const float r0 = *reinterpret_cast<const float*>(slb + kRowOff + (t0 << 2));
+                    const float rM = *reinterpret_cast<const float*>(slb + kRowOff + (iM << 2));
+                    const double2 pa = *reinterpret_cast<const double2*>(slb + ((t0 + 1) << 4));
+                    const double2 pb = *reinterpret_cast<const double2*>(slb + (iM << 4));
                     const double T0 = pb.x - pa.x;
                     const double T1 = (pb.y - pa.y) - (double)t0 * T0;
                     const double xM = a0d - (double)M, x1 = a0d - 1.0;
                     double St = fma(xM, (double)rM, fma(-x1, (double)r0, T0));
                     double Sw = fma(xM * xM, (double)rM, fma(-x1 * x1, (double)r0, fma(2.0 * a0d - 1.0, T0, -2.0 * T1)));
                     float Sr = rM - r0;
-                    const bool any = M >= 1;
-                    if (!(in_row && any)) { St = 0.0; Sw = 0.0; Sr = 0.f; }
                     // windows outside the staged row: boundaries straight from global memory
+                    // (a window without an inside boundary, M < 1, contributes nothing and is
+                    // skipped below)
                     const bool glob = use && !in_row;
-                    if (__ballot(glob)) {
+                    {
                         if (glob) {
                             // the same closed form, summing r_1..r_{M-1} straight from the
                             // residual row in global memory, eight loads in flight at a time
@@ -517,10 +522,9 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                             St = fma(xMg, (double)qM, fma(-x1g, (double)q0, g0));
                             Sw = fma(xMg * xMg, (double)qM, fma(-x1g * x1g, (double)q0, fma(2.0 * a0d - 1.0, g0, -2.0 * g1)));
                             Sr = qM - q0;
-                            if (M < 1) { St = 0.0; Sw = 0.0; Sr = 0.f; }
                         }
                     }
-                    if (use) {
+                    if (M >= 1) {                                // implies use
                         // C = P_f delta / (4 r); constant factors (P_f delta / 4, -2 rho / delta,
                         // delta / 4) are applied once per frame below
                         const float A = fmaf(-rho * rho, Sr, (float)Sw);

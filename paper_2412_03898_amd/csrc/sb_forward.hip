@@ -501,12 +501,13 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             if (KERNEL == SB_KERNEL_UNIFORM && qmode) {
                 // Integer tile.  Per ball: place this ball's window (flushing if needed),
                 // issue the seven row reads, run the next ball's FP64 set-up while the reads
-                // are in flight, then write the seven rows.  Balls are read from LDS two
-                // ahead, so the set-up never waits for the row reads.
+                // are in flight, then write the seven rows.  The ball after next is read from
+                // LDS at the end of each iteration, into the registers the set-up has just
+                // released (reading it earlier needs a second set of registers and a copy
+                // per ball).
                 FwdPair cur = prep(0);
                 BallS bn = sball[min(1, nb - 1)];
                 for (int i = 0; i < nb; ++i) {
-                    const BallS bnn = sball[min(i + 2, nb - 1)];
                     const bool part = cur.in_tile;
                     const int rows = max(cur.W, 5) + 2;           // the same in every lane
                     const bool in_lds = rows <= UCAP;
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                         nxt = setup(bn);
                     }
                     cur = nxt;
-                    bn = bnn;
+                    bn = sball[min(i + 2, nb - 1)];
                 }
             } else {
                 // FP32 tile; software pipeline: the set-up of ball i+1 overlaps the tile

@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
             const float rho = live ? bl.rhof : 0.f;
             const double rhod = live ? bl.rho : 0.0;
             const double c1 = p.t0fs + (rhod - 0.5);          // window start: floor(r / delta - c1)
+            const float nrr = -rho * rho, two_inv_delta = 2.f * inv_delta_f;
             const double r_in = rhod * (double)delta;          // sensor must be farther than this
             const bool w_ok = live && rhod < 1.0e6;
             const int W = w_ok ? (int)(2.0 * rhod) + 2 : 0;
@@ -527,9 +528,9 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                     if (M >= 1) {                                // implies use
                         // C = P_f delta / (4 r); constant factors (P_f delta / 4, -2 rho / delta,
                         // delta / 4) are applied once per frame below
-                        const float A = fmaf(-rho * rho, Sr, (float)Sw);
+                        const float A = fmaf(nrr, Sr, (float)Sw);
                         const float Bs = (float)St;
-                        const float q = (2.f * inv_delta_f) * Bs - A * inv_r;   // dL/dr / (C)
+                        const float q = two_inv_delta * Bs - A * inv_r;   // dL/dr / (C)
                         const float qr = q * inv_r * inv_r;                      // times 1/r for the direction
                         g5[0] = fmaf(qr, (float)dx, g5[0]);
                         g5[1] = fmaf(qr, (float)dy, g5[1]);

@@ -101,8 +101,8 @@ __device__ inline void add_window(float* c, int W, float x0, float rho, float C)
     } else {
         // Gaussian ball: eight samples per batch, all eight rows read before any is
         // written back (one LDS wait per batch instead of one per sample)
-        const float ce = -1.f / (2.f * rho * rho);
-        float Ep = __expf(x0 * x0 * ce), x = x0;
+        const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale: log2(e) / (2 rho^2)
+        float Ep = __builtin_amdgcn_exp2f(x0 * x0 * ce), x = x0;
         int j = 0;
         for (; j + 8 <= W; j += 8) {
             float o[8], v[8];
@@ -111,18 +111,30 @@ __device__ inline void add_window(float* c, int W, float x0, float rho, float C)
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 x -= 1.f;
-                const float E = __expf(x * x * ce);
+                const float E = __builtin_amdgcn_exp2f(x * x * ce);
                 v[u] = C * (E - Ep);
                 Ep = E;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) c[(j + u) * 64] = o[u] + v[u];
         }
-        for (; j < W; ++j) {
-            x -= 1.f;
-            const float E = __expf(x * x * ce);
-            c[j * 64] += C * (E - Ep);
-            Ep = E;
+        if (j < W) {
+            // the last 1..7 samples as one batch: rows past the window are neither read
+            // nor written
+            const int n = W - j;
+            float o[8], v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o[u] = (u < n) ? c[(j + u) * 64] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                x -= 1.f;
+                const float E = __builtin_amdgcn_exp2f(x * x * ce);
+                v[u] = C * (E - Ep);
+                Ep = E;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u < n) c[(j + u) * 64] = o[u] + v[u];
         }
     }
 }
@@ -213,8 +225,8 @@ __device__ inline bool add_window_global(float* row, int klo, int T, int W, floa
                                          float C) {
     bool clipped = false;
     float Qp = rho * rho;
-    const float ce = -1.f / (2.f * rho * rho);
-    float Ep = (KERNEL == SB_KERNEL_UNIFORM) ? 0.f : __expf(x * x * ce);
+    const float ce = -1.4426950408889634f / (2.f * rho * rho);   // exp2 scale
+    float Ep = (KERNEL == SB_KERNEL_UNIFORM) ? 0.f : __builtin_amdgcn_exp2f(x * x * ce);
     for (int j = 0; j < W; ++j) {
         x -= 1.f;
         float v;
@@ -224,7 +236,7 @@ __device__ inline bool add_window_global(float* row, int klo, int T, int W, floa
             v = C * (Qp - Q);
             Qp = Q;
         } else {
-            const float E = __expf(x * x * ce);
+            const float E = __builtin_amdgcn_exp2f(x * x * ce);
             v = C * (E - Ep);
             Ep = E;
         }

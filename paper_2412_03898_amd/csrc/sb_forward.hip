@@ -19,7 +19,8 @@
 // coalesced FP32 atomic per row.  Windows longer than the tile go to global
 // memory directly.  For the uniform sphere the tile normally holds the traces'
 // second differences as exact integers (see d2_window), so that a window costs
-// seven tile updates whatever its length; the flush integrates them back.
+// seven tile updates (LDS integer adds that return nothing) whatever its length;
+// the flush integrates them back.
 //
 // Trace of one ball in sample units (tau = (r - c t0)/delta, rho = R_f/delta):
 // with boundaries x_m = tau - k_lo + 1/2 - m, m = 0..W, between samples,
@@ -197,6 +198,25 @@ __device__ inline D2Win d2_window(int W, float x0, float rho, float Cs) {
     r.d[6] = e2;
     r.w2 = Wp - 2;
     return r;
+}
+
+// Adds a window's seven second differences to the lane's column (rows c0[0], c0[64],
+// c0[128] and c1[0] .. c1[192], in units of 64 floats per row) with LDS integer atomics
+// that return nothing: no read-back, so nothing waits on the LDS round trip.  The
+// column is the lane's own; a wave's LDS operations complete in order, so the flush's
+// reads see every add.  Integer addition wraps modulo 2^32, as the second-difference
+// form requires.
+__device__ inline void d2_add(uint32_t* c0, uint32_t* c1, const D2Win& dw) {
+    auto add = [](uint32_t* a, uint32_t v) {
+        __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    add(c0, dw.d[0]);
+    add(c0 + 64, dw.d[1]);
+    add(c0 + 128, dw.d[2]);
+    add(c1, dw.d[3]);
+    add(c1 + 64, dw.d[4]);
+    add(c1 + 128, dw.d[5]);
+    add(c1 + 192, dw.d[6]);
 }
 
 // A chunk ball as staged in LDS for the pair set-up: what depends on the ball only
@@ -512,8 +532,8 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             };
             if (KERNEL == SB_KERNEL_UNIFORM && qmode) {
                 // Integer tile.  Per ball: place this ball's window (flushing if needed),
-                // issue the seven row reads, run the next ball's FP64 set-up while the reads
-                // are in flight, then write the seven rows.  The ball after next is read from
+                // issue its seven LDS adds, and run the next ball's FP64 set-up while they
+                // complete (nothing waits on them).  The ball after next is read from
                 // LDS at the end of each iteration, into the registers the set-up has just
                 // released (reading it earlier needs a second set of registers and a copy
                 // per ball).
@@ -542,31 +562,13 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                         // set-up and the row updates interleave
                         const D2Win dw = d2_window<true>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
                         uint32_t* const c0 = twu + tr * 64 + lane;
-                        uint32_t* const c1 = c0 + dw.w2 * 64;
-                        const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
-                        const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
+                        d2_add(c0, c0 + dw.w2 * 64, dw);
                         nxt = setup(bn);
-                        c0[0] = o0 + dw.d[0];
-                        c0[64] = o1 + dw.d[1];
-                        c0[128] = o2 + dw.d[2];
-                        c1[0] = o3 + dw.d[3];
-                        c1[64] = o4 + dw.d[4];
-                        c1[128] = o5 + dw.d[5];
-                        c1[192] = o6 + dw.d[6];
                     } else {
                         if (in_lds) {
                             const D2Win dw = d2_window<false>(cur.W, part ? cur.xg : 0.f, cur.rhof, part ? cur.Cg * qs : 0.f);
                             uint32_t* const c0 = twu + tr * 64 + lane;
-                            uint32_t* const c1 = c0 + dw.w2 * 64;
-                            const uint32_t o0 = c0[0], o1 = c0[64], o2 = c0[128];
-                            const uint32_t o3 = c1[0], o4 = c1[64], o5 = c1[128], o6 = c1[192];
-                            c0[0] = o0 + dw.d[0];
-                            c0[64] = o1 + dw.d[1];
-                            c0[128] = o2 + dw.d[2];
-                            c1[0] = o3 + dw.d[3];
-                            c1[64] = o4 + dw.d[4];
-                            c1[128] = o5 + dw.d[5];
-                            c1[192] = o6 + dw.d[6];
+                            d2_add(c0, c0 + dw.w2 * 64, dw);
                         } else if (part) {
                             clipped |= add_window_global<KERNEL>(out_row, cur.klo, p.T, cur.W, cur.xg, cur.rhof, cur.Cg);
                         }

@@ -244,22 +244,27 @@ def test_window_lengths_two_to_forty():
     assert err <= SIG_TOL
 
 
-def test_sensors_among_the_balls():
-    """Sensors inside the cloud's box (outside every ball), all among the first 64: the
-    wave holding them keeps the FP32 tile, the other waves take the integer one."""
-    wl = tiny_scene(n_balls=900, n_sensors=200, seed=86)
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_sensors_among_the_balls(kernel):
+    """Sensors inside the cloud's box, all among the first 64: the wave holding them keeps
+    the FP32 tile, the other waves take the integer one.  Uniform spheres: every inner
+    sensor lies 0.5 mm outside every ball; Gaussian balls: farther than 10 std from every
+    centre, where the trace term the kernel leaves out is below 1e-21 of the peak."""
+    wl = tiny_scene(n_balls=900, n_sensors=200, seed=86, kernel=kernel)
     sens = wl.sensors.copy()
     rng = np.random.default_rng(86)
     inner = rng.choice(64, size=40, replace=False)     # all in the first 64-sensor wave
     b = wl.balls.astype(np.float64)
+    margin = b[3] + 0.5e-3 if kernel == 0 else 10.0 * b[3]
     for s in inner:
         while True:
             p = rng.uniform(-0.012, 0.012, size=3)
-            if np.min(np.linalg.norm(b[0:3] - p[:, None], axis=0) - b[3]) > 0.5e-3:
+            if np.min(np.linalg.norm(b[0:3] - p[:, None], axis=0) - margin) > 0.0:
                 break
         sens[:, s] = p.astype(np.float32)
     k0 = 0
-    n = synth.record_length_needed(0.060, 0.010, 0.4e-3, 0.5e-3, k0)
+    reach = 0.4e-3 if kernel == 0 else 2.0e-3            # largest radius, or 6 std x 2 (+10%)
+    n = synth.record_length_needed(0.060, 0.010, reach, 0.5e-3, k0)
     wl = _morton(with_(wl, sensors=sens, t0=0.0, n_samples=n))
     y, flags = gpu_forward(wl)
     ref = oracle.forward(wl)

@@ -322,6 +322,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 bs.rhof = bl.rhof;
                 bs.hf = (float)h;
                 bs.Wc = !valid ? 0 : (h >= 1.0e6 ? -1 : (int)(2.0 * h) + 2);
+                clipped |= valid && h >= 1.0e6;                  // a window longer than any record
                 sball[tid] = bs;
             }
             if (KERNEL == SB_KERNEL_UNIFORM) {
@@ -401,6 +402,10 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 qmode = __all(ok);
             }
             uint32_t* const twu = reinterpret_cast<uint32_t*>(tw);
+
+            // A pair without its window (sensor inside a uniform ball, or an arrival sample out
+            // of int32 range) sets one lane mask; the flags are told apart on a slow path.
+            bool bad = false;
 
             // Each lane's column covers samples o .. o + UCAP - 1 of its sensor.  The
             // balls are taken in chunk order (spatially coherent after slingbag_order);
@@ -502,9 +507,8 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 const double kl = floor(u);
                 const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
                 const bool use = active && valid && !too_long;
-                geometry |= use && !ok;
-                clipped |= (active && too_long) || (use && ok && !in_range);
                 f.in_tile = use && ok && in_range;               // the window exists (placed at apply)
+                bad |= use && !f.in_tile;
                 f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
                 f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
                 f.klo = in_range ? (int)kl : 0;
@@ -588,6 +592,20 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 }
             }
             flush();
+            if (__ballot(bad)) {
+                // rare: redo the pair tests of the chunk to raise the exact flags
+                for (int i = 0; i < nb; ++i) {
+                    const BallS bs = sball[i];
+                    const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
+                    const bool use = active && Wc > 0;
+                    float ri;
+                    const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
+                    const bool ok = r > bs.Rd;
+                    const double kl = floor(fma(r, p.inv_delta, -bs.c1));
+                    geometry |= use && !ok;
+                    clipped |= use && ok && !(fabs(kl) < 5.0e8);
+                }
+            }
         }
     }
     if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);

@@ -317,6 +317,21 @@ def test_nonfinite_ball_is_skipped_and_flagged():
     assert rel_l2(y.cpu().numpy(), ref) <= SIG_TOL
 
 
+def test_ball_longer_than_any_record_is_skipped_and_flagged():
+    """A ball whose window would span more than a million samples (radius 100 m) is left
+    out with the clipped flag; the other balls still match the oracle without it."""
+    wl = tiny_scene(n_balls=300, n_sensors=70, seed=93)
+    big = wl.balls.copy()
+    big[3, 17] = 100.0
+    y, flags = gpu_forward(with_(wl, balls=big))
+    keep = np.r_[0:17, 18:300]
+    ref = oracle.forward(with_(wl, balls=wl.balls[:, keep], ball_offset=np.array([0, 299])))
+    err = rel_l2(y, ref)
+    _say(f"ball longer than any record: rel-L2 {err:.3e} flags={flags}")
+    assert flags & 4
+    assert err <= SIG_TOL
+
+
 # ---------------------------------------------------------------- full sizes, sampled outputs
 # The GPU runs the whole problem (every ball, sensor and frame, default knobs);
 # the oracle computes the sampled (frame, sensor) rows.  For the adjoint the

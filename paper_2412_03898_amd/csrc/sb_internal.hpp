@@ -218,7 +218,7 @@ __device__ inline double dist64(double dx, double dy, double dz, float& ri) {
     ri = __builtin_amdgcn_rcpf(rf);
     const double r0 = (double)rf;
     const float e = (float)fma(-r0, r0, r2);
-    return r0 + (double)(e * (0.5f * ri));
+    return fma((double)(e * ri), 0.5, r0);
 }
 __device__ inline double dist64(double dx, double dy, double dz) {
     float ri;

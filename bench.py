@@ -29,8 +29,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Vector-ALU peak in lane operations (an FMA counts once; packed FP32 is not
-# generated in this build): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+# Vector-ALU peak in lane operations (an FMA counts once; packed FP32 is switched
+# off at compile time): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # 39.32 T lane-ops/s
 
 # Learning rates of Sec. 3.2 (coordinates, peak pressure, size, deformation).
@@ -331,7 +331,7 @@ def main():
                     help="fix the kernel knobs as COLUMN,OCCUPANCY,ITEMS instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the operator has no multi-GPU path in this build "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
 

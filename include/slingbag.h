@@ -77,7 +77,7 @@ extern "C" {
 #define SB_ERR_GEOMETRY     (-4)   /* reserved for geometry errors found on the host */
 #define SB_ERR_HIP          (-5)   /* a HIP runtime call failed (message in slingbag_last_error) */
 #define SB_ERR_DEVICE_FLAG  (-6)   /* slingbag_check found a device-side violation */
-#define SB_ERR_UNSUPPORTED  (-7)   /* valid request this build does not implement */
+#define SB_ERR_UNSUPPORTED  (-7)   /* valid request the library does not implement */
 
 /* ---- device flag bits (slingbag_check) ---- */
 #define SB_FLAG_GEOMETRY    1u     /* a sensor lay inside a uniform ball (pair skipped) */

@@ -377,6 +377,16 @@ def test_vessel_static_full_size_sampled():
     _full_size_sampled(wl, 16, 1, 6)
 
 
+def test_heart_ellipsoid_full_size_sampled():
+    """The heart phantom's Gaussian ellipsoid (10,667 Gaussian balls, Fourier pulsation, 17 frames,
+    1,024 sensors, 2,560 samples) at full size, with the default Gaussian knobs (256-row forward
+    column, 384-sample adjoint row); sampled every 64th sensor and 4th frame."""
+    slabs, ell = synth.heart_phantom()
+    wl = synth.apply_order(ell)
+    _say(f"heart ellipsoid full B={wl.n_balls} F={wl.n_frames} S={wl.n_sensors} T={wl.n_samples}")
+    _full_size_sampled(wl, 64, 4, 8)
+
+
 def test_vessel_4d_full_size_sampled():
     wl = synth.apply_order(synth.workload_vessel_4d())
     _say(f"vessel 4d full B={wl.n_balls} S={wl.n_sensors} F={wl.n_frames} T={wl.n_samples}")

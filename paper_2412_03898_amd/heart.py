@@ -24,7 +24,7 @@ import time
 import numpy as np
 import torch
 
-from . import ops, synth
+from . import ops, synth, tune
 from .binding import Problem
 from .ir import LR_DEF, LR_P, LR_POS, LR_R, IRLoop
 
@@ -82,7 +82,22 @@ def two_stage(n_static: int = 200, n_4d: int = 200, n_sensors: int = 1024, n_fra
               fit_half: float = 13e-3, fit_spacing: float = 1.0e-3, fit_std: float = 0.3e-3,
               p0: float = 0.02, lr_scale: float = 1.0, seed: int = 31, phantom_spacing: float = 0.5e-3,
               voxel: float = 0.25e-3, log=print) -> dict:
-    """The two-stage reconstruction of the heart phantom; returns the result record."""
+    """The two-stage reconstruction of the heart phantom; returns the result record.  The
+    kernel knobs are autotuned per stage and restored afterwards."""
+    from . import binding
+    keys = (binding.SB_TUNE_FWD_COLUMN, binding.SB_TUNE_ADJ_OCCUPANCY, binding.SB_TUNE_ADJ_ITEMS,
+            binding.SB_TUNE_FWD_GAUSS_COLUMN)
+    saved = [binding.tune_get(k) for k in keys]
+    try:
+        return _two_stage(n_static, n_4d, n_sensors, n_frames, fit_half, fit_spacing, fit_std, p0,
+                          lr_scale, seed, phantom_spacing, voxel, log)
+    finally:
+        for k, v in zip(keys, saved):
+            binding.tune(k, v)
+
+
+def _two_stage(n_static, n_4d, n_sensors, n_frames, fit_half, fit_spacing, fit_std, p0, lr_scale, seed,
+               phantom_spacing, voxel, log) -> dict:
     t_start = time.perf_counter()
     slabs, ell = synth.heart_phantom(n_sensors=n_sensors, n_frames=n_frames, spacing=phantom_spacing)
     pb_s, bs, _, ft, sens = ops.to_device(slabs)
@@ -103,6 +118,9 @@ def two_stage(n_static: int = 200, n_4d: int = 200, n_sensors: int = 1024, n_fra
     cloud, _, _ = ops.apply_order(pb1, cloud, None)
     ft1 = ft[f_ref:f_ref + 1].contiguous()
     m1 = measured[f_ref:f_ref + 1].contiguous()
+    # kernel knobs timed on each stage's own shapes (the 4D stage's Eq. 2 chain rule per work
+    # item wants fewer, larger sensor splits than a static frame)
+    tuning1 = tune.autotune(pb1, cloud, None, ft1, sens, cache=None)
     s1 = IRLoop(pb1, cloud, None, ft1, sens, m1, lrs=lrs)
     l1 = s1.run(n_static)
     s1.close()
@@ -111,6 +129,7 @@ def two_stage(n_static: int = 200, n_4d: int = 200, n_sensors: int = 1024, n_fra
     # ---- stage 2: 4D with the Gaussian-basis deformation from H = 0
     deform = torch.from_numpy(gauss_basis_start(B)).cuda()
     pb2 = _problem(slabs, 1, 2, 1, N_BASES, B, F)
+    tuning2 = tune.autotune(pb2, cloud, deform, ft, sens, cache=None)
     s2 = IRLoop(pb2, cloud, deform, ft, sens, measured, lrs=lrs)
     L_start = s2.full_loss()
     n_grid = int(round(2 * 24e-3 / voxel))
@@ -128,7 +147,8 @@ def two_stage(n_static: int = 200, n_4d: int = 200, n_sensors: int = 1024, n_fra
             "stage1_iters": n_static, "stage1_loss": [l1[0], l1[-1]],
             "stage2_iters": n_4d, "stage2_loss_all_frames": [L_start, L_end],
             "xy_map_corr_start": [round(c, 4) for c in corr0], "xy_map_corr_end": [round(c, 4) for c in corr1],
-            "lr_scale": lr_scale, "seconds": round(time.perf_counter() - t_start, 1)}
+            "lr_scale": lr_scale, "tuning": {"stage1": list(tuning1), "stage2": list(tuning2)},
+            "seconds": round(time.perf_counter() - t_start, 1)}
 
 
 def main():

@@ -225,39 +225,15 @@ __device__ inline double dist64(double dx, double dy, double dz) {
     return dist64(dx, dy, dz, ri);
 }
 
-// Window of one (ball, sensor) pair.  tau = (r - c t0)/delta is the arrival
-// sample; the window starts at sample k_lo = floor(tau - h + 1/2) (h = rho for the
-// uniform sphere, kGaussCut*rho for the Gaussian ball) so that boundary 0,
-// x_0 = tau - k_lo + 1/2, lies in [h, h + 1), and spans W = floor(2h) + 2 samples,
-// so that boundary W lies below -h: every nonzero sample is inside.  For the
-// uniform sphere the boundaries strictly inside (-rho, rho) are m = 1..m_hi,
-// m_hi = ceil(x_0 + rho) - 1; that decision is taken in FP64.
-template <int KERNEL>
-struct PairWin {
-    double r;        // ball-sensor distance
-    float ri;        // 1 / r in FP32
-    double a0;       // x_0
-    int klo, W, m_hi;
-    bool ok;         // sensor outside the uniform ball (r > 0 for the Gaussian ball)
-    bool in_range;   // |k_lo| and W small enough for int32 sample arithmetic
-};
-
-template <int KERNEL>
-__device__ inline PairWin<KERNEL> pair_window(const OpParams& p, double rho, double dx, double dy,
-                                              double dz) {
-    PairWin<KERNEL> w;
-    w.r = dist64(dx, dy, dz, w.ri);
-    const double h = (KERNEL == SB_KERNEL_UNIFORM) ? rho : (double)kGaussCut * rho;
-    w.ok = (KERNEL == SB_KERNEL_UNIFORM) ? (w.r > rho * (double)p.delta) : (w.r > 0.0);
-    const double tau = fma(w.r, p.inv_delta, -p.t0fs);
-    const double kl = floor(tau - h + 0.5);
-    w.in_range = fabs(kl) < 5.0e8 && h < 1.0e6;
-    w.klo = w.in_range ? (int)kl : 0;
-    w.W = w.in_range ? (int)(2.0 * h) + 2 : 0;
-    w.a0 = tau - kl + 0.5;
-    w.m_hi = (KERNEL == SB_KERNEL_UNIFORM && w.in_range) ? (int)ceil(w.a0 + rho) - 1 : 0;
-    return w;
-}
+// Window of one (ball, sensor) pair, as every kernel places it (inline, in its own
+// pair loop).  tau = (r - c t0)/delta is the arrival sample; the window starts at
+// sample k_lo = floor(tau - h + 1/2) (h = rho for the uniform sphere, kGaussCut*rho
+// for the Gaussian ball) so that boundary 0, x_0 = tau - k_lo + 1/2, lies in
+// [h, h + 1), and spans W = floor(2h) + 2 samples, so that boundary W lies below -h:
+// every nonzero sample is inside.  For the uniform sphere the boundaries strictly
+// inside (-rho, rho) are m = 1..m_hi, m_hi = ceil(x_0 + rho) - 1; that decision is
+// taken in FP64.  A pair is used only when the sensor lies outside the uniform ball
+// (r > 0 for the Gaussian ball) and |k_lo| stays far inside int32.
 
 // Wave-wide reductions (all 64 lanes participate).
 __device__ inline float wave_min(float v) {

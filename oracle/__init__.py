@@ -72,6 +72,10 @@ def _load():
                                      ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, d]
         lib.sbo_voxelize.restype = ctypes.c_int
+        lib.sbo_voxel_ties.argtypes = [ctypes.c_int64, d, d, d, d, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       P(ctypes.c_ubyte)]
+        lib.sbo_voxel_ties.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -215,6 +219,32 @@ def voxelize(kernel: int, attrs, grid, gauss_window: float = 10.0, n_threads: in
                           float(z0), float(h), float(gauss_window), int(n_threads), _ptr(vol))
     _check(st, "oracle voxelize")
     return vol
+
+
+def voxel_ties(attrs, grid):
+    """(mask [nz][ny][nx] bool, count): uniform-sphere voxels whose centre lies within the
+    rounding of two FP64 evaluations of d^2 of some ball's surface (sbo_voxel_ties), where
+    the inside test d <= R is decided by rounding rather than by the geometry."""
+    lib = _load()
+    a = _f64(attrs)
+    nx, ny, nz, x0, y0, z0, h = grid
+    mask = np.zeros((int(nz), int(ny), int(nx)), dtype=np.uint8)
+    n = lib.sbo_voxel_ties(a.shape[1], _ptr(np.ascontiguousarray(a[0])), _ptr(np.ascontiguousarray(a[1])),
+                           _ptr(np.ascontiguousarray(a[2])), _ptr(np.ascontiguousarray(a[3])), int(nx), int(ny),
+                           int(nz), float(x0), float(y0), float(z0), float(h),
+                           mask.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)))
+    if n < 0:
+        raise OracleError("oracle voxel ties: bad grid")
+    return mask.astype(bool), int(n)
+
+
+def voxel_ties_scene(wl, t: float, grid, balls=None, deform=None):
+    """voxel_ties() of a single-scene workload's balls deformed by Eq. 1 at frame time t."""
+    import types
+    B = (wl.balls if balls is None else balls).shape[1]
+    one = types.SimpleNamespace(**{**vars(wl), "frame_t": np.array([t], dtype=np.float32),
+                                   "ball_offset": np.array([0, B]), "frame_offset": np.array([0, 1])})
+    return voxel_ties(deformed(one, 0, balls=balls, deform=deform), grid)
 
 
 def voxelize_scene(wl, t: float, grid, balls=None, deform=None, **kw) -> np.ndarray:

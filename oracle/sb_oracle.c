@@ -375,7 +375,8 @@ int sbo_adjoint(const sbo_problem* p, int n_scenes, const int64_t* ball_offset,
  *  evaluated out to `gauss_window` R_b; <= 0 means every voxel).
  *  Inputs are the (already deformed) attributes in FP64, one array per
  *  attribute.  Planes k are independent, so they are split over threads; each
- *  voxel's sum runs over the balls in order.
+ *  voxel's sum runs over the balls in order.  The voxel centre and the squared
+ *  distance are the plain expressions x0 + i h and dx^2 + dy^2 + dz^2.
  */
 int sbo_voxelize(int kernel, int64_t n, const double* x, const double* y, const double* z,
                  const double* R, const double* P, int32_t nx, int32_t ny, int32_t nz,
@@ -386,7 +387,7 @@ int sbo_voxelize(int kernel, int64_t n, const double* x, const double* y, const 
     if (n_threads > 0) omp_set_num_threads(n_threads);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t k = 0; k < nz; ++k) {
-        const double zc = fma((double)k, h, z0);
+        const double zc = z0 + (double)k * h;
         for (int64_t b = 0; b < n; ++b) {
             /* balls with non-finite or invalid attributes contribute nothing */
             if (!isfinite(x[b]) || !isfinite(y[b]) || !isfinite(z[b]) || !isfinite(R[b]) || !isfinite(P[b]) ||
@@ -407,10 +408,10 @@ int sbo_voxelize(int kernel, int64_t n, const double* x, const double* y, const 
                 if (hi_j < j1) j1 = (int64_t)hi_j;
             }
             for (int64_t j = j0; j <= j1; ++j) {
-                const double dy = fma((double)j, h, y0) - y[b];
+                const double dy = (y0 + (double)j * h) - y[b];
                 for (int64_t i = i0; i <= i1; ++i) {
-                    const double dx = fma((double)i, h, x0) - x[b];
-                    const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    const double dx = (x0 + (double)i * h) - x[b];
+                    const double d2 = dx * dx + dy * dy + dz * dz;
                     double v;
                     if (kernel == 0) v = (d2 <= R[b] * R[b]) ? P[b] : 0.0;
                     else v = (d2 <= reach * reach) ? P[b] * exp(-d2 / (2.0 * R[b] * R[b])) : 0.0;
@@ -420,4 +421,50 @@ int sbo_voxelize(int kernel, int64_t n, const double* x, const double* y, const 
         }
     }
     return SBO_OK;
+}
+
+/*
+ * Tie voxels of the uniform-sphere grid: voxels whose centre lies so close to
+ * some ball's surface that the inside test d^2 <= R^2 depends on how d^2 is
+ * rounded.  Two FP64 evaluations of d^2 (any order of the operations, with or
+ * without fused multiply-adds) differ by at most a few units in the last place
+ * of the coordinates and of d^2; a voxel counts as a tie when
+ *   |d^2 - R^2| <= 64 eps (R^2 + 2 R L),   eps = 2^-52,
+ * L the largest coordinate magnitude of the voxel centre and the ball centre.
+ * mask[k][j][i] is set to 1 for ties (0 elsewhere); returns the tie count.
+ */
+int64_t sbo_voxel_ties(int64_t n, const double* x, const double* y, const double* z, const double* R,
+                       int32_t nx, int32_t ny, int32_t nz, double x0, double y0, double z0, double h,
+                       unsigned char* mask) {
+    if (nx < 1 || ny < 1 || nz < 1 || !(h > 0.0) || n < 0) return -1;
+    memset(mask, 0, (size_t)nx * ny * nz);
+    const double eps = 2.220446049250313e-16;
+    int64_t count = 0;
+    for (int64_t b = 0; b < n; ++b) {
+        if (!isfinite(x[b]) || !isfinite(y[b]) || !isfinite(z[b]) || !isfinite(R[b]) || !(R[b] > 0.0)) continue;
+        const double reach = R[b] * 1.001;
+        const double lo_i = floor((x[b] - reach - x0) / h) - 1, hi_i = ceil((x[b] + reach - x0) / h) + 1;
+        const double lo_j = floor((y[b] - reach - y0) / h) - 1, hi_j = ceil((y[b] + reach - y0) / h) + 1;
+        const double lo_k = floor((z[b] - reach - z0) / h) - 1, hi_k = ceil((z[b] + reach - z0) / h) + 1;
+        const int64_t i0 = lo_i > 0 ? (int64_t)lo_i : 0, i1 = hi_i < nx - 1 ? (int64_t)hi_i : nx - 1;
+        const int64_t j0 = lo_j > 0 ? (int64_t)lo_j : 0, j1 = hi_j < ny - 1 ? (int64_t)hi_j : ny - 1;
+        const int64_t k0 = lo_k > 0 ? (int64_t)lo_k : 0, k1 = hi_k < nz - 1 ? (int64_t)hi_k : nz - 1;
+        for (int64_t k = k0; k <= k1; ++k)
+            for (int64_t j = j0; j <= j1; ++j)
+                for (int64_t i = i0; i <= i1; ++i) {
+                    const double cx = x0 + (double)i * h, cy = y0 + (double)j * h, cz = z0 + (double)k * h;
+                    const double dx = cx - x[b], dy = cy - y[b], dz = cz - z[b];
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    double L = fabs(cx);
+                    const double cand[5] = {fabs(cy), fabs(cz), fabs(x[b]), fabs(y[b]), fabs(z[b])};
+                    for (int c = 0; c < 5; ++c) L = cand[c] > L ? cand[c] : L;
+                    const double tol = 64.0 * eps * (R[b] * R[b] + 2.0 * R[b] * L);
+                    unsigned char* m = mask + ((size_t)k * ny + j) * nx + i;
+                    if (fabs(d2 - R[b] * R[b]) <= tol && !*m) {
+                        *m = 1;
+                        ++count;
+                    }
+                }
+    }
+    return count;
 }

@@ -3,7 +3,10 @@
 
 Bars: relative L2 <= 1e-5 over the volume and over each projection; for the
 uniform sphere the inside test is FP64 on both sides, so the set of voxels a
-ball reaches is identical.
+ball reaches is identical, except at tie voxels: centres so close to a ball's
+surface that two FP64 evaluations of d^2 (the oracle's plain sum, the kernel's
+fused multiply-adds) may decide differently (oracle.voxel_ties).  Those are
+counted and reported (none are expected), and excluded from the set comparison.
 """
 
 import sys
@@ -48,10 +51,13 @@ def compare(wl, t, grid, balls=None):
     rmaps = oracle.maps(ref)
     err = rel_l2(got, ref)
     merr = [rel_l2(g, r) for g, r in zip(gmaps, rmaps)]
-    _say(f"volume rel-L2 {err:.2e}, maps {['%.2e' % e for e in merr]}, nonzero {int((ref != 0).sum())}")
-    assert err <= TOL and max(merr) <= TOL
+    ties = 0
     if wl.kernel == 0:
-        np.testing.assert_array_equal(got != 0, ref != 0)
+        tie, ties = oracle.voxel_ties_scene(wl, t, grid, balls=balls)
+        np.testing.assert_array_equal((got != 0)[~tie], (ref != 0)[~tie])
+    _say(f"volume rel-L2 {err:.2e}, maps {['%.2e' % e for e in merr]}, nonzero {int((ref != 0).sum())}, "
+         f"tie voxels {ties}")
+    assert err <= TOL and max(merr) <= TOL
     return flags
 
 

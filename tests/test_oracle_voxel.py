@@ -31,6 +31,21 @@ def test_uniform_sphere_lattice_count(r_over_h, count):
     assert set(np.unique(v)) <= {0.0, 2.0}
 
 
+@pytest.mark.parametrize("r_over_h, ties", [(0.99, 0), (1.0, 6), (1.5, 0), (2.0, 6), (2.5, 0)])
+def test_tie_voxels_are_the_lattice_points_on_the_sphere(r_over_h, ties):
+    """Tie voxels (inside test decided by rounding) of a ball centred on a voxel of the
+    binary-exact grid are exactly the lattice points with i^2 + j^2 + k^2 = r^2, where
+    d = R holds exactly: the 6 axis neighbours for r = 1 and r = 2, none for r = 0.99,
+    1.5 or 2.5 (r^2 not a sum of three squares of integers, or not an integer)."""
+    R = r_over_h * H
+    mask, n = oracle.voxel_ties(ball(0.0, 0.0, 0.0, R, 1.0), GRID)
+    i = np.arange(9) - 4
+    K, J, I = np.meshgrid(i, i, i, indexing="ij")
+    exact = (I * I + J * J + K * K) * H * H == R * R
+    assert n == ties == int(exact.sum())
+    np.testing.assert_array_equal(mask, exact)
+
+
 def test_gaussian_mass():
     """sum of voxels x h^3 = P (2 pi)^(3/2) a^3 (Riemann sum of a Gaussian with a = 4 h,
     grid reaching past 8 a on every side)."""

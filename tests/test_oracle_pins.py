@@ -94,6 +94,64 @@ def test_bruteforce_poisson(kernel, n_mu, tol):
     assert outside <= (0.0 if kernel == 0 else 1e-9 * amax)
 
 
+# ---------------------------------------------------------------- Gaussian ball, sensor near the ball
+# The Gaussian ball's incoming (r + ct) term is below the double range at every sensor of
+# the workloads; these pins put the sensor 2.5 std from the centre, with the record
+# starting at t = 0, where that term carries half of the pressure.
+def _near_gauss(fs, a=0.2e-3, r_over_a=2.5, T=None, P=1.3):
+    delta = synth.C_SOUND / fs
+    r = r_over_a * a
+    if T is None:
+        T = int(math.ceil((r + 12 * a) / delta)) + 4
+    return with_(tiny_scene(n_balls=1, n_sensors=1, kernel=1), fs=fs, t0=0.5 / fs, n_samples=T,
+                 sensors=np.array([[r], [0.0], [0.0]]),
+                 balls=np.array([[0.0], [0.0], [0.0], [a], [P]], dtype=np.float64))
+
+
+def test_gauss_ball_initial_condition_at_the_sensor():
+    """The wave equation's solution starts from the initial pressure: p(x_s, 0+) =
+    P exp(-r^2/2a^2) at a sensor r from the centre (zero initial velocity, so p changes as
+    t^2).  The first sample averages p over [0, dt]; with c dt = a/53 the t^2 term moves it
+    by ~2e-4 relative.  The outgoing (r - ct) term alone gives half of p0, a sign error in
+    the incoming term gives ~0, so either mistake fails by orders of magnitude."""
+    fs = 400e6
+    wl = _near_gauss(fs)
+    y = oracle.forward(wl)[0, 0]
+    r, a, P = float(wl.sensors[0, 0]), float(wl.balls[3, 0]), float(wl.balls[4, 0])
+    p0 = P * math.exp(-r * r / (2 * a * a))
+    assert y[0] == pytest.approx(p0, rel=1e-3)
+    assert y[0] != pytest.approx(0.5 * p0, rel=0.1)
+
+
+def test_gauss_ball_near_sensor_bruteforce():
+    """Sensor 2.5 std from a Gaussian ball, record from t = 0: the closed form (both
+    terms) against quadrature of Poisson's formula over every sample."""
+    wl = _near_gauss(synth.FS)
+    y = oracle.forward(wl)[0]
+    yb = brute.forward_bruteforce(wl.balls, wl.sensors, wl.c, wl.fs, wl.t0, wl.n_samples, 1,
+                                  n_mu=20_000, n_phi=2)
+    assert rel_l2(yb, y) < 5e-6
+    # the incoming term is not negligible here: the first samples carry a large share
+    assert abs(y[0, 0]) > 0.05 * np.abs(y).max()
+
+
+def test_gauss_ball_near_sensor_gradient():
+    """Gradient of 1/2|y - d|^2 with the incoming term active (sensor 2.5 std from the
+    centre) against central differences of the FP64 loss, for position, std and pressure."""
+    wl = _near_gauss(synth.FS)
+    d = oracle.forward(wl, balls=wl.balls * np.array([[1.0], [1.0], [1.0], [1.07], [0.9]]) +
+                       np.array([[2e-5], [0.0], [0.0], [0.0], [0.0]]))
+    y = oracle.forward(wl)
+    gb, _ = oracle.adjoint(wl, y - d)
+    balls = wl.balls.astype(np.float64)
+    for a, e in ((0, 1e-9), (1, 1e-9), (3, 1e-9), (4, 1e-6)):
+        bp, bm = balls.copy(), balls.copy()
+        bp[a, 0] += e
+        bm[a, 0] -= e
+        fd = (_loss_at(wl, d, bp, None) - _loss_at(wl, d, bm, None)) / (2 * e)
+        assert gb[a, 0] == pytest.approx(fd, rel=2e-5, abs=1e-9 * np.abs(gb).max()), a
+
+
 # ---------------------------------------------------------------- invariances
 def test_superposition_and_homogeneity():
     wl = tiny_scene(n_balls=8, n_sensors=6, seed=5)

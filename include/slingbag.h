@@ -57,8 +57,14 @@
  * device can see (a sensor inside a uniform ball, a non-finite or
  * non-positive deformed size, a negative deformed pressure) skip the affected
  * ball and raise a sticky device flag, read back by slingbag_check().
- * Entry points are safe to call from several host threads on distinct
- * streams.
+ *
+ * Concurrency: the library keeps one set of scratch buffers per device (the
+ * flag word, the loss partials, the ordering buffers), shared by every stream
+ * of that device and bound into every captured plan.  Calls (and plan
+ * replays) on one device must therefore not overlap in time: issue them on one
+ * stream, or order the streams.  Host-side state (tuning knobs, timing, the
+ * per-thread error message) is guarded, so entry points may be called from
+ * several host threads.
  */
 #ifndef SLINGBAG_H
 #define SLINGBAG_H
@@ -74,7 +80,8 @@ extern "C" {
 #define SB_ERR_INVALID_ARG  (-1)   /* null pointer, unknown enum, bad scalar */
 #define SB_ERR_SHAPE        (-2)   /* offsets not a prefix sum, too many scenes/terms, size overflow */
 #define SB_ERR_NONFINITE    (-3)   /* non-finite c, fs or t0 */
-#define SB_ERR_GEOMETRY     (-4)   /* reserved for geometry errors found on the host */
+#define SB_ERR_GEOMETRY     (-4)   /* reserved, not returned: geometry violations are found on the
+                                      device and reported as SB_FLAG_GEOMETRY by slingbag_check */
 #define SB_ERR_HIP          (-5)   /* a HIP runtime call failed (message in slingbag_last_error) */
 #define SB_ERR_DEVICE_FLAG  (-6)   /* slingbag_check found a device-side violation */
 #define SB_ERR_UNSUPPORTED  (-7)   /* valid request the library does not implement */
@@ -134,8 +141,8 @@ int slingbag_forward(const sb_config* cfg, const sb_batch* batch,
 /* L2 data loss (Sec. 2.2).  residual[i] = signals[i] - measured[i] for all
  * F_total*S*T entries (residual may alias signals or measured), and *loss
  * (a DEVICE double) = 1/2 sum residual^2, reduced in a fixed order (the
- * result does not depend on timing).  Scratch: a per-device buffer of block
- * partials, allocated on first use and grown as needed. */
+ * result does not depend on timing).  Scratch: a fixed per-device buffer of
+ * block partials (16 KB), allocated on the first call on the device. */
 int slingbag_loss(const sb_config* cfg, const sb_batch* batch,
                   const float* signals, const float* measured, float* residual,
                   double* loss, void* stream);

@@ -57,9 +57,16 @@ __global__ __launch_bounds__(256, OCC) void adjoint_gauss_kernel(OpParams p) {
         const int s_begin = it.split * p.s_per_split;
         const int ns = min(p.S - s_begin, p.s_per_split);     // sensors of this split (<= kAdjMaxSplit)
 
-        // ---- rank the chunk's balls by base size; wave w takes ranks 64w..64w+63
+        // ---- rank the chunk's balls by base size; wave w takes ranks 64w..64w+63.
+        // (key, index) must be a strict total order so that the ranks form a
+        // permutation: a NaN or +inf size (a ball that deform_ball skips) takes the
+        // padding key, ordered by index before the padding threads.
         __syncthreads();
-        const float Ri = tid < nb ? p.balls[3 * p.B + first + tid] : 3.0e38f;
+        float Ri = 3.0e38f;
+        if (tid < nb) {
+            const float R = p.balls[3 * p.B + first + tid];
+            Ri = R < 3.0e38f ? R : 3.0e38f;
+        }
         sR[tid] = Ri;
         __syncthreads();
         int rank = 0;

@@ -132,20 +132,30 @@ struct Tuning {
     int adj_occ = 4;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
     int adj_items = 8192;      // adjoint items the sensor split aims for
 };
-static Tuning g_tune;
+static Tuning g_tune;   // guarded by g_mu
 
-static TileCfg pick_forward_tiles(int kernel) {
+static Tuning tuning() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tune;
+}
+
+static void set_tuning(const Tuning& t) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune = t;
+}
+
+static TileCfg pick_forward_tiles(int kernel, const Tuning& tu) {
     TileCfg tc;
-    const bool long_col = kernel != SB_KERNEL_UNIFORM && g_tune.fwd_gauss_ucap == 256;
+    const bool long_col = kernel != SB_KERNEL_UNIFORM && tu.fwd_gauss_ucap == 256;
     tc.nw = long_col ? 2 : 4;
     tc.g = 64 * tc.nw;
-    tc.ucap = kernel == SB_KERNEL_UNIFORM ? g_tune.fwd_ucap : g_tune.fwd_gauss_ucap;
+    tc.ucap = kernel == SB_KERNEL_UNIFORM ? tu.fwd_ucap : tu.fwd_gauss_ucap;
     return tc;
 }
 
-static TileCfg pick_adjoint_tiles(int kernel) {
+static TileCfg pick_adjoint_tiles(int kernel, const Tuning& tu) {
     TileCfg tc;
-    tc.nw = kernel == SB_KERNEL_UNIFORM ? g_tune.adj_occ : 2;
+    tc.nw = kernel == SB_KERNEL_UNIFORM ? tu.adj_occ : 2;
     tc.g = 256;
     tc.ucap = kernel == SB_KERNEL_UNIFORM ? 128 : 384;
     return tc;
@@ -204,7 +214,8 @@ constexpr int64_t kAdjMaxSplitHost = 256;   // sensors per adjoint item at most 
 
 // Adjoint items: (scene, chunk of 256 balls, split of the sensors); frames inside.
 // The sensors are split so that there are enough items to fill the chip.
-static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh) {
+static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batch, const Shape& sh,
+                         const Tuning& tu) {
     fill_common(p, cfg, batch, sh);
     int64_t chunks = 0;
     for (int i = 0; i < batch->n_scenes; ++i) {
@@ -212,7 +223,7 @@ static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batc
         s.n_groups = (s.n_balls + 255) / 256;
         if (s.n_frames > 0) chunks += s.n_groups;
     }
-    const int64_t target = g_tune.adj_items;
+    const int64_t target = tu.adj_items;
     int64_t n_split = chunks > 0 ? (target + chunks - 1) / chunks : 1;
     const int64_t max_split = sh.S >= 8 ? sh.S / 8 : 1;
     if (n_split > max_split) n_split = max_split;
@@ -309,7 +320,7 @@ int slingbag_forward(const sb_config* cfg, const sb_batch* batch, const float* b
     hipError_t e = launch_fill(signals, sh.F * sh.S * sh.T, 0.f, s);
     if (e != hipSuccess) return hip_fail(e, "fill(signals)");
     if (sh.B == 0 || sh.F == 0) return SB_OK;
-    const TileCfg tc = pick_forward_tiles(cfg->kernel);
+    const TileCfg tc = pick_forward_tiles(cfg->kernel, tuning());
     OpParams p;
     fill_forward(p, cfg, batch, sh, tc);
     p.balls = balls;
@@ -365,9 +376,10 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* b
         e = launch_fill(grad_deform, 5 * (int64_t)sh.M * sh.B, 0.f, s);
     if (e != hipSuccess) return hip_fail(e, "fill(grads)");
     if (sh.B == 0 || sh.F == 0) return SB_OK;
-    const TileCfg tc = pick_adjoint_tiles(cfg->kernel);
+    const Tuning tu = tuning();
+    const TileCfg tc = pick_adjoint_tiles(cfg->kernel, tu);
     OpParams p;
-    fill_adjoint(p, cfg, batch, sh);
+    fill_adjoint(p, cfg, batch, sh, tu);
     p.balls = balls;
     p.deform = deform;
     p.frame_t = frame_t;
@@ -547,38 +559,43 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
     if (!choice) return fail(SB_ERR_INVALID_ARG, "choice is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int reps = 2;
-    const Tuning saved = g_tune;
+    const Tuning saved = tuning();
+    Tuning cur = saved;          // the candidate being timed, published to the calls below
     float best = 3.0e38f, ms = 0.f;
     // the column knob of the problem's kernel: 64 / 128 (uniform sphere), 128 / 256 (Gaussian ball)
     const bool uni = cfg->kernel == SB_KERNEL_UNIFORM;
-    int& col_knob = uni ? g_tune.fwd_ucap : g_tune.fwd_gauss_ucap;
+    int& col_knob = uni ? cur.fwd_ucap : cur.fwd_gauss_ucap;
     int best_col = col_knob;
     for (int col : {64, 128, 256}) {
         if (uni ? col == 256 : col == 64) continue;
         col_knob = col;
+        set_tuning(cur);
         st = time_ms(s, reps, [&] { return slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream); }, &ms);
-        if (st) { g_tune = saved; return st; }
+        if (st) { set_tuning(saved); return st; }
         if (ms < best) { best = ms; best_col = col; }
     }
     col_knob = best_col;
+    set_tuning(cur);
     // the forward output serves as a finite residual for timing the adjoint
     st = slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream);
-    if (st) { g_tune = saved; return st; }
+    if (st) { set_tuning(saved); return st; }
     best = 3.0e38f;
-    int best_occ = g_tune.adj_occ, best_items = g_tune.adj_items;
+    int best_occ = cur.adj_occ, best_items = cur.adj_items;
     for (int occ : {2, 3, 4}) {
         for (int items : {2048, 4096, 8192, 16384}) {
             if (cfg->kernel != SB_KERNEL_UNIFORM && occ != 2) continue;
-            g_tune.adj_occ = occ;
-            g_tune.adj_items = items;
+            cur.adj_occ = occ;
+            cur.adj_items = items;
+            set_tuning(cur);
             st = time_ms(s, reps, [&] { return slingbag_adjoint(cfg, batch, balls, deform, frame_t, sensors, signals,
                                                                  grad_balls, grad_deform, stream); }, &ms);
-            if (st) { g_tune = saved; return st; }
+            if (st) { set_tuning(saved); return st; }
             if (ms < best) { best = ms; best_occ = occ; best_items = items; }
         }
     }
-    g_tune.adj_occ = best_occ;
-    g_tune.adj_items = best_items;
+    cur.adj_occ = best_occ;
+    cur.adj_items = best_items;
+    set_tuning(cur);
     choice[0] = best_col;
     choice[1] = best_occ;
     choice[2] = best_items;

@@ -317,6 +317,35 @@ def test_nonfinite_ball_is_skipped_and_flagged():
     assert rel_l2(y.cpu().numpy(), ref) <= SIG_TOL
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_nonfinite_size_is_skipped_by_the_adjoint(kernel):
+    """A NaN and a +inf size inside one 256-ball chunk (the Gaussian-ball adjoint ranks the
+    chunk's balls by size): both balls are skipped and flagged, their gradients stay zero,
+    and every other ball's gradient matches the oracle without them."""
+    import torch
+    from paper_2412_03898_amd import binding, ops
+    wl = tiny_scene(n_balls=300, n_sensors=70, seed=85, kernel=kernel)
+    bad = wl.balls.copy()
+    bad[3, 7] = np.nan
+    bad[3, 130] = np.inf
+    keep = np.r_[0:7, 8:130, 131:300]
+    sub = with_(wl, balls=wl.balls[:, keep], ball_offset=np.array([0, len(keep)]))
+    rng = np.random.default_rng(86)
+    ref_y = oracle.forward(sub)
+    res = (rng.normal(size=ref_y.shape) * np.abs(ref_y).max()).astype(np.float32)
+    _say(f"nonfinite sizes in the adjoint, kernel={kernel}")
+    pb, balls, deform, ft, sens = ops.to_device(with_(wl, balls=bad))
+    gb, _ = ops.adjoint(pb, balls, deform, ft, sens, torch.from_numpy(res).cuda())
+    torch.cuda.synchronize()
+    with pytest.raises(binding.SlingbagError) as ei:
+        ops.check()
+    assert ei.value.status == binding.SB_ERR_DEVICE_FLAG
+    g = gb.cpu().numpy().astype(np.float64)
+    assert np.all(g[:, [7, 130]] == 0.0)
+    ref_gb, _ = oracle.adjoint(sub, res.astype(np.float64))
+    assert_grads(sub, (g[:, keep], None), (ref_gb, None))
+
+
 def test_ball_longer_than_any_record_is_skipped_and_flagged():
     """A ball whose window would span more than a million samples (radius 100 m) is left
     out with the clipped flag; the other balls still match the oracle without it."""

@@ -114,3 +114,50 @@ def test_graph_replays_match_eager():
         assert rel_l2(g.signals.cpu().numpy(), oracle.forward(wl2)) <= 1e-5
     finally:
         g.close()
+
+
+def test_graph_replays_on_uneven_batch_match_oracle():
+    """The captured step on an uneven batch of three scenes (300 balls x 2 frames, an empty
+    scene with 3 frames, 1,000 balls x 1 frame; Fourier deformation): four replays with an
+    eager in-place parameter update and synchronisations between them, each replay's
+    signals, loss and gradient groups against the oracle of the current parameters."""
+    import sys
+    import torch
+    from helpers import tiny_scene
+    from paper_2412_03898_amd import ops
+    a = tiny_scene(n_balls=300, n_sensors=70, n_frames=2, basis=1, seed=171)
+    b = tiny_scene(n_balls=1000, n_sensors=70, n_frames=1, basis=1, seed=172)
+    wl = with_(a, balls=np.concatenate([a.balls, b.balls], axis=1),
+               deform=np.concatenate([a.deform, b.deform], axis=2),
+               frame_t=np.concatenate([a.frame_t, np.array([0.3, 0.7, 0.9], np.float32), b.frame_t]),
+               ball_offset=np.array([0, 300, 300, 1300]), frame_offset=np.array([0, 2, 5, 6]))
+    d_np = oracle.forward(wl, balls=synth.perturbed(wl.balls, 173)).astype(np.float32)
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    d = torch.from_numpy(d_np).cuda()
+    g = ops.StepGraph(pb, balls, deform, ft, sens, d)
+    try:
+        for rep in range(4):
+            print(f"[gpu-graph] uneven batch replay {rep}", flush=True)
+            balls[4].mul_(1.0 + 0.01 * rep)        # eager work between replays, in place
+            deform[0].add_(1e-6)
+            torch.cuda.synchronize()
+            Lg, gbg, gdg = g.run()
+            torch.cuda.synchronize()
+            assert ops.check() == 0
+            cur = with_(wl, balls=balls.cpu().numpy(), deform=deform.cpu().numpy())
+            y_ref = oracle.forward(cur)
+            L_ref, r_ref = oracle.loss(y_ref, d_np)
+            gb_ref, gd_ref = oracle.adjoint(cur, r_ref)
+            y = g.signals.cpu().numpy()
+            assert np.abs(y[2:5]).max() == 0.0, rep
+            assert rel_l2(y, y_ref) <= 1e-5, rep
+            assert float(Lg.item()) == pytest.approx(L_ref, rel=2e-5), rep
+            gb, gd = gbg.cpu().numpy(), gdg.cpu().numpy()
+            groups = [(gb[0:3], gb_ref[0:3]), (gb[3], gb_ref[3]), (gb[4], gb_ref[4])]
+            groups += [(gd[k], gd_ref[k]) for k in range(5)]
+            errs = [rel_l2(x, r) for x, r in groups]
+            print(f"[gpu-graph] replay {rep}: grad rel-L2 max {max(errs):.2e}", flush=True)
+            sys.stdout.flush()
+            assert max(errs) <= 1e-4, (rep, errs)
+    finally:
+        g.close()

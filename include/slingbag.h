@@ -147,6 +147,21 @@ int slingbag_loss(const sb_config* cfg, const sb_batch* batch,
                   const float* signals, const float* measured, float* residual,
                   double* loss, void* stream);
 
+/* slingbag_loss for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and error behaviour, bit-identical residual and
+ * *loss, but no allocation of any kind.  The block partials live in a fixed
+ * device array of 2,048 doubles (16 KiB), which each device that loads the
+ * library holds until the process ends; the reduction always uses 2,048
+ * blocks, so every signal size fits (a larger need would return
+ * SB_ERR_SHAPE).  Every partial is rewritten by each call, so nothing carries
+ * over from the last call.  All calls on one device share that array: calls
+ * that overlap in time on one device (on different streams, or replays of
+ * graphs that captured this call) race and return wrong losses; order them. */
+int slingbag_loss_noalloc(const sb_config* cfg, const sb_batch* batch,
+                          const float* signals, const float* measured, float* residual,
+                          double* loss, void* stream);
+
 /* Adjoint (Sec. 2.2: gradient of the L2 loss with respect to all baseline
  * attributes and deformation parameters).  Given residual = dL/dsignals,
  * writes grad_balls [5][B_total] = dL/dballs and grad_deform [5][M][B_total]

@@ -62,6 +62,7 @@ _VP = ctypes.c_void_p
 _SIGS = {
     "slingbag_forward": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP, _VP],
     "slingbag_loss": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP],
+    "slingbag_loss_noalloc": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP],
     "slingbag_adjoint": [ctypes.POINTER(Config), ctypes.POINTER(Batch), _VP, _VP, _VP, _VP, _VP,
                          _VP, _VP, _VP],
     "slingbag_check": [_VP, ctypes.POINTER(ctypes.c_uint32)],
@@ -171,6 +172,11 @@ def forward(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, si
 def loss(pb: Problem, signals: int, measured: int, residual: int, loss_out: int, stream: int = 0):
     _check(load().slingbag_loss(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), signals, measured,
                                 residual, loss_out, stream))
+
+
+def loss_noalloc(pb: Problem, signals: int, measured: int, residual: int, loss_out: int, stream: int = 0):
+    _check(load().slingbag_loss_noalloc(ctypes.byref(pb.cfg), ctypes.byref(pb.batch), signals, measured,
+                                        residual, loss_out, stream))
 
 
 def adjoint(pb: Problem, balls: int, deform: int, frame_t: int, sensors: int, residual: int,

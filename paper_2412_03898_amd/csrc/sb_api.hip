@@ -356,6 +356,28 @@ int slingbag_loss(const sb_config* cfg, const sb_batch* batch, const float* sign
     return SB_OK;
 }
 
+int slingbag_loss_noalloc(const sb_config* cfg, const sb_batch* batch, const float* signals,
+                          const float* measured, float* residual, double* loss, void* stream) {
+    Shape sh;
+    int st = validate_config(cfg, sh);
+    if (st) return st;
+    if ((st = validate_batch(batch, sh))) return st;
+    if (!loss) return fail(SB_ERR_INVALID_ARG, "loss is NULL");
+    const int64_t n = sh.F * sh.S * sh.T;
+    if (n > 0 && (!signals || !measured || !residual))
+        return fail(SB_ERR_INVALID_ARG, "signals / measured / residual is NULL");
+    // the reduction always runs loss_blocks() blocks, one partial each, whatever n
+    if (loss_blocks() > noalloc_partials_capacity())
+        return fail(SB_ERR_SHAPE, "loss needs %d partials, the fixed scratch holds %d", loss_blocks(),
+                    noalloc_partials_capacity());
+    double* partials = nullptr;
+    hipError_t e = noalloc_partials(&partials);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(loss scratch)");
+    e = launch_loss(signals, measured, residual, n, partials, loss_blocks(), loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "loss kernels");
+    return SB_OK;
+}
+
 int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* balls,
                      const float* deform, const float* frame_t, const float* sensors,
                      const float* residual, float* grad_balls, float* grad_deform, void* stream) {

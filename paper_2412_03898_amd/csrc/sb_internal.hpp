@@ -326,6 +326,8 @@ hipError_t launch_fill(float* ptr, int64_t n, float v, hipStream_t st);
 hipError_t launch_loss(const float* y, const float* d, float* r, int64_t n, double* partials,
                        int n_blocks, double* loss, hipStream_t st);
 int loss_blocks();
+hipError_t noalloc_partials(double** out);   // device address of the fixed partials array
+int noalloc_partials_capacity();
 hipError_t launch_voxelize(const OpParams& p, int kernel, int nx, int ny, int nz, double x0, double y0,
                            double z0, double h, float t, float* vol, hipStream_t st);
 hipError_t launch_map(const float* vol, int nx, int ny, int nz, float* xy, float* yz, float* xz, hipStream_t st);

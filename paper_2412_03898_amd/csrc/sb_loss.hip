@@ -4,6 +4,9 @@
 // on scheduling.  Also the plain fill kernel used to clear outputs (a kernel
 // rather than a memset so that the sequence can be captured in a graph).
 
+#include <mutex>
+#include <vector>
+
 #include "sb_internal.hpp"
 
 namespace sb {
@@ -12,6 +15,38 @@ constexpr int kLossThreads = 256;
 constexpr int kLossBlocks = 2048;
 
 int loss_blocks() { return kLossBlocks; }
+
+// Block partials of slingbag_loss_noalloc: a fixed device array, so that the call
+// allocates nothing (each device that loads the library holds one copy, 16 KiB, until
+// the process ends).  In host code `scratch` names a host-side stand-in, not device
+// memory: its device address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is handed to kernels.
+constexpr int kNoallocPartials = 2048;
+static __device__ __align__(256) double scratch[kNoallocPartials];
+static_assert(kLossBlocks <= kNoallocPartials, "one partial per loss block");
+
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_addr;   // per device: device address of `scratch`
+
+int noalloc_partials_capacity() { return kNoallocPartials; }
+
+hipError_t noalloc_partials(double** out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 __global__ __launch_bounds__(256) void fill_kernel(float* __restrict__ ptr, int64_t n, float v) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -218,9 +218,12 @@ int slingbag_check(void* stream, uint32_t* flags);
  * one hipGraphLaunch on any stream.  The plan binds the buffers and the tuning
  * knobs of its creation: the caller may change their contents (for instance
  * update balls and deform in place between runs) but not their addresses or
- * the shapes.  No memsets are recorded (outputs are cleared by kernels).  The
- * plan owns only the graph; slingbag_plan_destroy releases it (NULL is a
- * no-op). */
+ * the shapes.  No memsets are recorded (outputs are cleared by kernels).  A
+ * plan created while timing is on (slingbag_timing) also records an event
+ * node before and after its forward, loss and adjoint kernels, and every
+ * replay while timing is on times them into the same pool as direct calls.
+ * The plan owns the graph (and those nodes' own events);
+ * slingbag_plan_destroy releases them (NULL is a no-op). */
 typedef struct sb_plan sb_plan;
 int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const float* balls,
                          const float* deform, const float* frame_t, const float* sensors,
@@ -272,7 +275,9 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
  * recorded events and returns, per kind [forward, adjoint, loss, adam], the
  * summed kernel milliseconds in total_ms[4] and the launch count in
  * launches[4] (HOST arrays), then resets the counters.  At most 8192 launches
- * per kind are recorded between reads.  Not for use under graph capture. */
+ * per kind are recorded between reads.  Replays of a plan created with timing
+ * on count like direct calls (see slingbag_plan_create); other graph captures
+ * record no timing. */
 int slingbag_timing(int enable);
 int slingbag_timing_read(double* total_ms, int64_t* launches);
 

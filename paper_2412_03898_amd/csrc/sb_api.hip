@@ -258,10 +258,35 @@ struct Timing {
 };
 static Timing g_timing;
 
+// A plan captured while timing is on times its launches too.  During the capture
+// each mark is an empty marker kernel; afterwards an event record node (with a
+// placeholder event) is added after every marker, ahead of the marker's successor,
+// and every replay points those nodes at a fresh pair of events from the pool, so
+// the launches of a replayed graph are timed like direct ones.
+__global__ void plan_mark_kernel() {}
+
+struct CaptureTiming {
+    hipEvent_t ev[kTimeKinds][2] = {};         // placeholders
+    hipGraphNode_t node[kTimeKinds][2] = {};   // the event record nodes that record them
+    std::vector<int> marks;                    // kind * 2 + which, in capture order
+    bool failed = false;
+};
+static thread_local CaptureTiming* g_capture = nullptr;   // set by slingbag_plan_create
+
 static void time_mark(int kind, int which, hipStream_t st) {
     if (!g_timing.enabled) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return;
+    if (cs != hipStreamCaptureStatusNone) {
+        if (g_capture && g_capture->ev[kind][which]) {
+            hipLaunchKernelGGL(plan_mark_kernel, dim3(1), dim3(64), 0, st);
+            if (hipGetLastError() == hipSuccess)
+                g_capture->marks.push_back(kind * 2 + which);
+            else
+                g_capture->failed = true;
+        }
+        return;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     int slot = g_timing.used[kind];
     if (slot >= kTimingSlots) return;
@@ -682,7 +707,96 @@ struct sb_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = -1;
+    bool timed = false;          // captured with timing on: the nodes below exist
+    bool on_pool = false;        // the nodes currently record pool events (not the placeholders)
+    CaptureTiming tm;
 };
+
+// Destroys the placeholder events of a plan's timing record.
+static void release_capture_timing(CaptureTiming& tm) {
+    for (int k = 0; k < kTimeKinds; ++k)
+        for (int w = 0; w < 2; ++w)
+            if (tm.ev[k][w]) {
+                (void)hipEventDestroy(tm.ev[k][w]);
+                tm.ev[k][w] = nullptr;
+            }
+}
+
+// After the capture: walk the captured chain (one stream: every node has at most one
+// dependent), and after the i-th marker kernel insert an event record node for the
+// i-th mark, on which the marker's successor then also depends.
+static int add_timing_nodes(hipGraph_t graph, CaptureTiming& tm) {
+    size_t n = 0;
+    hipError_t e = hipGraphGetRootNodes(graph, nullptr, &n);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphGetRootNodes");
+    if (n != 1) return fail(SB_ERR_HIP, "captured plan has %zu root nodes, expected one chain", n);
+    hipGraphNode_t node = nullptr;
+    if ((e = hipGraphGetRootNodes(graph, &node, &n)) != hipSuccess) return hip_fail(e, "hipGraphGetRootNodes");
+    std::vector<hipGraphNode_t> chain;
+    while (node) {
+        chain.push_back(node);
+        size_t nd = 0;
+        if ((e = hipGraphNodeGetDependentNodes(node, nullptr, &nd)) != hipSuccess)
+            return hip_fail(e, "hipGraphNodeGetDependentNodes");
+        if (nd > 1) return fail(SB_ERR_HIP, "captured plan is not a chain");
+        hipGraphNode_t next = nullptr;
+        if (nd == 1 && (e = hipGraphNodeGetDependentNodes(node, &next, &nd)) != hipSuccess)
+            return hip_fail(e, "hipGraphNodeGetDependentNodes");
+        node = nd == 1 ? next : nullptr;
+    }
+    size_t mi = 0;
+    for (size_t i = 0; i < chain.size(); ++i) {
+        hipGraphNodeType ty;
+        if ((e = hipGraphNodeGetType(chain[i], &ty)) != hipSuccess) return hip_fail(e, "hipGraphNodeGetType");
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        if ((e = hipGraphKernelNodeGetParams(chain[i], &kp)) != hipSuccess)
+            return hip_fail(e, "hipGraphKernelNodeGetParams");
+        if (kp.func != reinterpret_cast<void*>(plan_mark_kernel)) continue;
+        if (mi >= tm.marks.size()) return fail(SB_ERR_HIP, "more timing markers in the plan than marks");
+        const int k = tm.marks[mi] / 2, w = tm.marks[mi] % 2;
+        ++mi;
+        hipGraphNode_t ev = nullptr;
+        if ((e = hipGraphAddEventRecordNode(&ev, graph, &chain[i], 1, tm.ev[k][w])) != hipSuccess)
+            return hip_fail(e, "hipGraphAddEventRecordNode");
+        if (i + 1 < chain.size() && (e = hipGraphAddDependencies(graph, &ev, &chain[i + 1], 1)) != hipSuccess)
+            return hip_fail(e, "hipGraphAddDependencies");
+        tm.node[k][w] = ev;
+    }
+    if (mi != tm.marks.size()) return fail(SB_ERR_HIP, "timing markers of the plan not found");
+    return SB_OK;
+}
+
+// Before a replay: point the plan's timing nodes at the next pool slot of each kind
+// (timing on) or back at the placeholders (timing off, or the pool full).
+static int retarget_timing_nodes(sb_plan* plan) {
+    if (!plan->timed) return SB_OK;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    const bool on = g_timing.enabled && g_timing.device == plan->device && dev == plan->device;
+    if (!on && !plan->on_pool) return SB_OK;
+    bool any_pool = false;
+    for (int k = 0; k < kTimeKinds; ++k) {
+        if (!plan->tm.node[k][0] || !plan->tm.node[k][1]) continue;
+        hipEvent_t a = plan->tm.ev[k][0], b = plan->tm.ev[k][1];
+        const int slot = g_timing.used[k];
+        const bool take = on && slot < kTimingSlots;
+        if (take) {
+            a = g_timing.ev[k][2 * slot];
+            b = g_timing.ev[k][2 * slot + 1];
+        }
+        hipError_t e = hipGraphExecEventRecordNodeSetEvent(plan->exec, plan->tm.node[k][0], a);
+        if (e == hipSuccess) e = hipGraphExecEventRecordNodeSetEvent(plan->exec, plan->tm.node[k][1], b);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphExecEventRecordNodeSetEvent");
+        if (take) {
+            g_timing.used[k] = slot + 1;
+            any_pool = true;
+        }
+    }
+    plan->on_pool = any_pool;
+    return SB_OK;
+}
 
 int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const float* balls,
                          const float* deform, const float* frame_t, const float* sensors,
@@ -698,28 +812,51 @@ int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const floa
     DeviceState* ds;
     if ((st = device_state(&ds))) return st;   // per-device buffers exist before capture
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    // with timing on, the timed launches are captured between event record nodes
+    CaptureTiming tm;
+    const bool timed = g_timing.enabled;
+    hipError_t e = hipSuccess;
+    if (timed) {
+        for (int k : {(int)kTimeForward, (int)kTimeLoss, (int)kTimeAdjoint})
+            for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipEventCreate(&tm.ev[k][w]);
+        if (e != hipSuccess) {
+            release_capture_timing(tm);
+            return hip_fail(e, "hipEventCreate(plan timing)");
+        }
+    }
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release_capture_timing(tm);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    g_capture = timed ? &tm : nullptr;
     st = slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream);
     if (st == SB_OK) st = slingbag_loss(cfg, batch, signals, measured, residual, loss, stream);
     if (st == SB_OK)
         st = slingbag_adjoint(cfg, batch, balls, deform, frame_t, sensors, residual, grad_balls, grad_deform, stream);
+    g_capture = nullptr;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
+    if (st == SB_OK && tm.failed) st = fail(SB_ERR_HIP, "capturing the plan's timing markers failed");
+    if (st == SB_OK && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
+    if (st == SB_OK && timed) st = add_timing_nodes(graph, tm);
     if (st != SB_OK) {
         if (graph) (void)hipGraphDestroy(graph);
+        release_capture_timing(tm);
         return st;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(graph);
+        release_capture_timing(tm);
         return hip_fail(e, "hipGraphInstantiate");
     }
     sb_plan* plan = new sb_plan;
     plan->graph = graph;
     plan->exec = exec;
+    plan->timed = timed;
+    plan->tm = tm;
     (void)hipGetDevice(&plan->device);
     *out = plan;
     return SB_OK;
@@ -727,6 +864,8 @@ int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const floa
 
 int slingbag_plan_run(sb_plan* plan, void* stream) {
     if (!plan || !plan->exec) return fail(SB_ERR_INVALID_ARG, "plan is NULL");
+    int st = retarget_timing_nodes(plan);
+    if (st) return st;
     hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return SB_OK;
@@ -737,6 +876,7 @@ int slingbag_plan_destroy(sb_plan* plan) {
     hipError_t e = hipSuccess;
     if (plan->exec) e = hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    release_capture_timing(plan->tm);
     delete plan;
     if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
     return SB_OK;

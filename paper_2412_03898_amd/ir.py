@@ -105,7 +105,8 @@ class IRLoop:
         self.decay_step, self.decay_rate = int(decay_step), float(decay_rate)
         self.iteration = 0
         self.losses: list[float] = []
-        self.graph = ops.StepGraph(pb, balls, deform, frame_t, sensors, measured) if use_graph else None
+        self.graph = (ops.StepGraph(pb, balls, deform, frame_t, sensors, measured, in_place=True)
+                      if use_graph else None)
         if self.graph is None:
             self.y = torch.empty_like(measured)
             self.r = torch.empty_like(measured)
@@ -221,11 +222,17 @@ class IRLoop:
         torch.cuda.synchronize()
 
 
-def _per_frame_static(wl, balls_np, deform_np):
-    """Per-frame static attributes of a Fourier-deformed scene (Eq. 1 with the Fourier
-    series, additive position, scaled size and pressure), materialised in FP64 and stored
-    as FP32: the input of the frame-by-frame path."""
+def materialise_frames(wl, balls_np, deform_np):
+    """Per-frame static attributes of a Fourier-deformed single scene (Eq. 1 with the
+    Fourier series: additive position, scaled size and pressure), evaluated in FP64
+    and stored as FP32 [5][B] arrays, one per frame: the inputs of the frame-by-frame
+    path.  Rounding the deformed positions to FP32 moves each arrival time by at most
+    about 1e-9 m / delta; the per-frame path's forward stays within 1e-5 (relative L2)
+    of the FP64 4D forward (tested)."""
     b = balls_np.astype(np.float64)
+    out = []
+    if deform_np is None:
+        return [np.ascontiguousarray(balls_np.astype(np.float32)) for _ in range(wl.n_frames)]
     D = deform_np.astype(np.float64)
     for f in range(wl.n_frames):
         t = float(wl.frame_t[f])
@@ -234,7 +241,63 @@ def _per_frame_static(wl, balls_np, deform_np):
         x = b.copy()
         x[0:3] += h[0:3]
         x[3:5] *= 1.0 + h[3:5]
-        yield np.ascontiguousarray(x.astype(np.float32))
+        out.append(np.ascontiguousarray(x.astype(np.float32)))
+    return out
+
+
+class PerFramePath:
+    """Frame-by-frame IR path on one GPU: every frame of a single scene is an independent
+    static scene with its own attributes [5][B] (materialised by materialise_frames) and
+    Adam state, and each iteration runs one forward, loss, adjoint and Adam step (three
+    parameter groups) per frame, with the learning rates of Sec. 3.2.  This is the plain
+    alternative to the batched 4D step: F static launches of each kernel instead of one
+    launch over all frames, and 5 F attributes per ball instead of 5 + 5 M."""
+
+    def __init__(self, wl, sensors, measured, frames_np, lrs=(LR_POS, LR_R, LR_P)):
+        from .binding import Problem
+        self.F, self.S, self.T = wl.n_frames, wl.n_sensors, wl.n_samples
+        B = frames_np[0].shape[1]
+        self.pb = Problem(wl.kernel, 0, 0, 0, self.S, self.T, wl.c, wl.fs, wl.t0,
+                          np.array([0, B]), np.array([0, 1]))
+        self.sensors, self.measured = sensors, measured
+        dev = measured.device
+        self.t0 = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.balls = [torch.from_numpy(x).to(dev) for x in frames_np]
+        self.y = torch.empty((1, self.S, self.T), dtype=torch.float32, device=dev)
+        self.L = torch.empty((), dtype=torch.float64, device=dev)
+        self.grads = [torch.empty_like(x) for x in self.balls]
+        self.moments = [[(torch.zeros_like(x[0:3]), torch.zeros_like(x[0:3])),
+                         (torch.zeros_like(x[3]), torch.zeros_like(x[3])),
+                         (torch.zeros_like(x[4]), torch.zeros_like(x[4]))] for x in self.balls]
+        self.lrs = lrs
+        self.iteration = 0
+
+    def step(self) -> None:
+        self.iteration += 1
+        inf = float("inf")
+        for f in range(self.F):
+            x, g = self.balls[f], self.grads[f]
+            ops.forward(self.pb, x, None, self.t0, self.sensors, out=self.y)
+            ops.loss(self.pb, self.y, self.measured[f:f + 1], residual=self.y, loss_out=self.L)
+            ops.adjoint(self.pb, x, None, self.t0, self.sensors, self.y, grad_balls=g)
+            groups = ((x[0:3], g[0:3], self.lrs[0], -inf), (x[3], g[3], self.lrs[1], R_MIN),
+                      (x[4], g[4], self.lrs[2], 0.0))
+            for (p, gg, lr, lo), (m, v) in zip(groups, self.moments[f]):
+                ops.adam_(p, gg, m, v, lr, self.iteration, lo=lo)
+
+    def time_ms(self, iters: int, warmup: int = 1, log=None) -> float:
+        """Mean ms per iteration over `iters` iterations after `warmup` untimed ones."""
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(iters):
+            self.step()
+            if log is not None:
+                torch.cuda.synchronize()
+                log(f"[ir] per-frame iteration {i + 1}")
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / iters * 1e3
 
 
 def large_ir(iters: int = 200, per_frame_iters: int = 3, tuning=None, n_balls: int = 1_000_000,
@@ -317,47 +380,16 @@ def large_ir(iters: int = 200, per_frame_iters: int = 3, tuning=None, n_balls: i
 
 
 def _per_frame_path(wl, pb, balls, ft, sens, measured, iters, log) -> dict:
-    """Frame-by-frame path: every frame an independent static scene with its own
-    materialised attributes, one forward, loss, adjoint and Adam per frame."""
-    from .binding import Problem
+    """The frame-by-frame path from the zero-coefficient start (each frame's attributes
+    equal the base attributes), timed over `iters` iterations."""
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats()
-    B = wl.n_balls
-    pf = Problem(wl.kernel, 0, 0, 0, wl.n_sensors, wl.n_samples, wl.c, wl.fs, wl.t0,
-                 np.array([0, B]), np.array([0, 1]))
-    t0 = torch.zeros(1, dtype=torch.float32, device="cuda")
-    # frames at the zero-coefficient start, which the batched run also starts from
-    zero = np.zeros((5, 2 * wl.n_terms, B), dtype=np.float32)
-    fb = [torch.from_numpy(x).cuda() for x in _per_frame_static(wl, balls.cpu().numpy(), zero)]
-    fy = torch.empty((1, wl.n_sensors, wl.n_samples), dtype=torch.float32, device="cuda")
-    fr = torch.empty_like(fy)
-    fL = torch.empty((), dtype=torch.float64, device="cuda")
-    fg = [torch.empty_like(x) for x in fb]
-    fstate = [[(torch.zeros_like(x[0:3]), torch.zeros_like(x[0:3])), (torch.zeros_like(x[3]), torch.zeros_like(x[3])),
-               (torch.zeros_like(x[4]), torch.zeros_like(x[4]))] for x in fb]
-
-    def one(it):
-        for f in range(wl.n_frames):
-            ops.forward(pf, fb[f], None, t0, sens, out=fy)
-            ops.loss(pf, fy, measured[f:f + 1], residual=fr, loss_out=fL)
-            ops.adjoint(pf, fb[f], None, t0, sens, fr, grad_balls=fg[f])
-            x, g = fb[f], fg[f]
-            for (p, gg, lr, lo), (m, v) in zip(((x[0:3], g[0:3], LR_POS, -float("inf")), (x[3], g[3], LR_R, R_MIN),
-                                                (x[4], g[4], LR_P, 0.0)), fstate[f]):
-                ops.adam_(p, gg, m, v, lr, it + 1, lo=lo)
-
-    one(0)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for it in range(1, iters + 1):
-        one(it)
-        torch.cuda.synchronize()
-        log(f"[ir] per-frame iteration {it}")
-    ms = (time.perf_counter() - t) / iters * 1e3
+    path = PerFramePath(wl, sens, measured, materialise_frames(wl, balls.cpu().numpy(), None))
+    ms = path.time_ms(iters, warmup=1, log=log)
     ops.check()
     rec = {"ms_per_iter": round(ms, 2), "iterations_timed": iters,
            "peak_mem_mb_torch": round(torch.cuda.max_memory_allocated() / 2**20, 1)}
-    del fb, fg, fstate
+    del path
     torch.cuda.empty_cache()
     return rec
 

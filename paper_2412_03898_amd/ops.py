@@ -96,15 +96,19 @@ class StepGraph:
 
     Binds the given tensors: update their contents in place between runs (e.g. the
     optimiser step), never reallocate them.  Needs a non-default stream (capture).
+    With in_place=True the residual overwrites the signals in one buffer (the loss
+    allows the alias), which saves one [F][S][T] array; `signals` then holds the
+    residual after each run.
     """
 
-    def __init__(self, pb: Problem, balls, deform, frame_t, sensors, measured, stream=None):
+    def __init__(self, pb: Problem, balls, deform, frame_t, sensors, measured, stream=None,
+                 in_place: bool = False):
         B, F, S, T, M = _shapes(pb)
         dev = balls.device
         self.pb = pb
         self.tensors = (balls, deform, frame_t, sensors, measured)
         self.signals = torch.empty((F, S, T), dtype=torch.float32, device=dev)
-        self.residual = torch.empty_like(self.signals)
+        self.residual = self.signals if in_place else torch.empty_like(self.signals)
         self.loss = torch.empty((), dtype=torch.float64, device=dev)
         self.grad_balls = torch.empty((5, B), dtype=torch.float32, device=dev)
         self.grad_deform = torch.empty((5, M, B), dtype=torch.float32, device=dev) if M else None

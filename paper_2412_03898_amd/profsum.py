@@ -5,6 +5,7 @@ usage:
   python -m paper_2412_03898_amd.profsum counters <out.txt> <title> <note> <command1> <csv1> [<command2> <csv2> ...]
 
   python -m paper_2412_03898_amd.profsum traffic <out.json> <kernel> <workload> <fetch.csv> <write.csv> <fetch_scale> <write_scale> <fetch_cmd> <write_cmd> <source>...
+  python -m paper_2412_03898_amd.profsum sq <out.json> <kernel> <workload> <counter.csv> <cmd> <source>...
 
 `traffic` records the HBM bytes per dispatch of one kernel (dispatches whose name
 contains <kernel>), scaled by the copy-calibration factors, together with a
@@ -13,6 +14,10 @@ figure only while those sources are unchanged.
 
 Counter tables keep only the library's own kernels (names containing "sb::")
 and the runtime's copy kernel used to calibrate the memory counters.
+
+`sq` records the mean per dispatch of every counter in one --pmc run for one
+kernel (for instance SQ_INSTS_VALU, the issued vector instructions), with the
+same source digest.
 
 `stats` tabulates a --kernel-trace --stats summary; `counters` averages each
 counter of one or more --pmc counter_collection.csv files per kernel and lists
@@ -92,13 +97,27 @@ def traffic(out, kernel, workload, fetch_csv, write_csv, fetch_scale, write_scal
         f.write("\n")
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch recorded for (kernel, workload) under profiles/, or None when
-    there is no record or the kernel's sources changed since the counters were taken."""
+def sq(out, kernel, workload, csv_path, command, sources):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if kernel in r["Kernel_Name"]:
+            agg[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    if not agg:
+        raise SystemExit(f"no dispatch of {kernel} in {csv_path}")
+    rec = {"kernel": kernel, "workload": workload,
+           "counters": {k: round(sum(v) / len(v), 1) for k, v in sorted(agg.items())},
+           "dispatches": max(len(v) for v in agg.values()), "command": command, "sources": sources,
+           "source_sha256": source_digest(sources)}
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+
+
+def _record_for(suffix: str, kernel: str, workload: str):
     if not os.path.isdir(PROFILES):
         return None
     for name in sorted(os.listdir(PROFILES)):
-        if not name.endswith("_traffic.json"):
+        if not name.endswith(suffix):
             continue
         with open(os.path.join(PROFILES, name)) as f:
             rec = json.load(f)
@@ -109,8 +128,22 @@ def traffic_for(kernel: str, workload: str):
                 return None
         except OSError:
             return None
-        return rec["bytes_per_launch"]
+        return rec
     return None
+
+
+def sq_for(kernel: str, workload: str, counter: str = "SQ_INSTS_VALU"):
+    """Mean per dispatch of an SQ counter recorded for (kernel, workload) under profiles/,
+    or None when there is no record or the kernel's sources changed since."""
+    rec = _record_for("_sq.json", kernel, workload)
+    return None if rec is None else rec["counters"].get(counter)
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch recorded for (kernel, workload) under profiles/, or None when
+    there is no record or the kernel's sources changed since the counters were taken."""
+    rec = _record_for("_traffic.json", kernel, workload)
+    return None if rec is None else rec["bytes_per_launch"]
 
 
 def main():
@@ -124,6 +157,9 @@ def main():
     elif mode == "traffic":
         a = sys.argv[2:]
         traffic(*a[:9], sources=a[9:])
+    elif mode == "sq":
+        a = sys.argv[2:]
+        sq(*a[:5], sources=a[5:])
     else:
         raise SystemExit(__doc__)
 

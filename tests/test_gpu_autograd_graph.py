@@ -161,3 +161,52 @@ def test_graph_replays_on_uneven_batch_match_oracle():
             assert max(errs) <= 1e-4, (rep, errs)
     finally:
         g.close()
+
+
+def test_graph_replays_are_timed():
+    """A plan created with timing on times its forward, loss and adjoint at every replay
+    (event nodes retargeted to fresh pool events per replay): one launch of each per
+    replay, durations close to those of the same kernels called directly, and the
+    replayed results unchanged by the timing nodes."""
+    import torch
+    from paper_2412_03898_amd import binding, ops
+    # large enough that each kernel runs for about a tenth of a millisecond
+    wl = synth.apply_order(synth.workload_vessel_4d(n_balls=20000, n_sensors=256, n_frames=4))
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    d = torch.zeros((pb.n_frames, 256, wl.n_samples), dtype=torch.float32, device="cuda")
+    binding.timing(True)
+    try:
+        binding.timing_read()
+        g = ops.StepGraph(pb, balls, deform, ft, sens, d)
+        try:
+            reps = 5
+            for _ in range(reps):
+                g.run()
+            torch.cuda.synchronize()
+            tg = binding.timing_read()
+            for k in ("forward", "loss", "adjoint"):
+                assert tg[k][1] == reps and tg[k][0] > 0.0, (k, tg[k])
+            y = ops.forward(pb, balls, deform, ft, sens)
+            L, r = ops.loss(pb, y, d)
+            gb, gd = ops.adjoint(pb, balls, deform, ft, sens, r)
+            for _ in range(reps - 1):
+                ops.forward(pb, balls, deform, ft, sens, out=y)
+                ops.adjoint(pb, balls, deform, ft, sens, r, grad_balls=gb, grad_deform=gd)
+            torch.cuda.synchronize()
+            te = binding.timing_read()
+            for k in ("forward", "adjoint"):
+                mg, me = tg[k][0] / tg[k][1], te[k][0] / te[k][1]
+                print(f"[gpu-graph] {k}: replayed {mg * 1e3:.1f} us, direct {me * 1e3:.1f} us", flush=True)
+                assert 0.5 * me <= mg <= 2.0 * me, (k, mg, me)
+            assert float(g.loss.item()) == pytest.approx(float(L.item()), rel=1e-6)
+            assert rel_l2(g.grad_balls.cpu().numpy(), gb.cpu().numpy()) <= 1e-5
+            # timing off: replays record nothing
+            binding.timing(False)
+            g.run()
+            torch.cuda.synchronize()
+            assert all(n == 0 for _, n in binding.timing_read().values())
+        finally:
+            g.close()
+    finally:
+        binding.timing(False)
+        ops.check()

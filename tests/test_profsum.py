@@ -34,3 +34,22 @@ def test_committed_record_is_consistent():
             assert abs(rec["bytes_per_launch"] - want) <= 0.05 * 1024 * (rec["fetch_scale"] + rec["write_scale"])
             for s in rec["sources"]:
                 assert os.path.exists(os.path.join(profsum.ROOT, s))
+
+
+def test_sq_record_follows_sources(tmp_path, monkeypatch):
+    root = tmp_path
+    (root / "profiles").mkdir()
+    src = root / "k.hip"
+    src.write_text("kernel v1\n")
+    monkeypatch.setattr(profsum, "ROOT", str(root))
+    monkeypatch.setattr(profsum, "PROFILES", str(root / "profiles"))
+    csv_path = root / "pmc.csv"
+    csv_path.write_text("Kernel_Name,Counter_Name,Counter_Value\n"
+                        "void sb::k<1>(x),SQ_INSTS_VALU,100\nvoid sb::k<1>(x),SQ_INSTS_VALU,300\n"
+                        "void sb::k<1>(x),SQ_WAVES,8\nvoid sb::other(x),SQ_INSTS_VALU,5\n")
+    profsum.sq(str(root / "profiles" / "k_w_sq.json"), "k<1>", "w", str(csv_path), "cmd", ["k.hip"])
+    assert profsum.sq_for("k<1>", "w") == 200.0
+    assert profsum.sq_for("k<1>", "w", "SQ_WAVES") == 8.0
+    assert profsum.sq_for("k<1>", "other") is None
+    src.write_text("kernel v2\n")
+    assert profsum.sq_for("k<1>", "w") is None

@@ -103,7 +103,7 @@ extern "C" {
 /* ---- limits ---- */
 #define SB_MAX_SCENES       32
 #define SB_MAX_FOURIER      8      /* harmonics K */
-#define SB_MAX_GAUSS_BASES  16     /* bases N per attribute */
+#define SB_MAX_GAUSS_BASES  128    /* bases N per attribute */
 
 typedef struct sb_config {
     int32_t kernel;      /* SB_KERNEL_* */
@@ -166,7 +166,13 @@ int slingbag_loss_noalloc(const sb_config* cfg, const sb_batch* batch,
  * attributes and deformation parameters).  Given residual = dL/dsignals,
  * writes grad_balls [5][B_total] = dL/dballs and grad_deform [5][M][B_total]
  * = dL/ddeform (both overwritten; grad_deform may be NULL only for STATIC).
- * Per-frame deformed attributes are recomputed here, never stored. */
+ * Per-frame deformed attributes are recomputed here, never stored.  The
+ * 2-harmonic Fourier series (and STATIC) apply the chain rule inside the
+ * adjoint kernel; every other basis sums the derivatives with respect to each
+ * ball's deformed attributes at every frame (5 floats per ball and frame) in a
+ * per-device buffer, allocated on first use and grown as needed (not under
+ * graph capture: slingbag_plan_create reserves it), and applies the chain rule
+ * once per ball in a second kernel. */
 int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch,
                      const float* balls, const float* deform, const float* frame_t,
                      const float* sensors, const float* residual,

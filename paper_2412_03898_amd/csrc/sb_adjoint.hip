@@ -268,31 +268,33 @@ __global__ __launch_bounds__(256, OCC) void adjoint_gauss_kernel(OpParams p) {
                     g5[4] += dLdP;
                 }
             }
-            // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame
+            // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame, or
+            // (two-phase) this split's share of dL/d(deformed attributes) to the scratch
             if (live) {
-                float base[5];
-                for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
-                for (int a = 0; a < 5; ++a) {
-                    const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
-                    const float hh = (float)eval_H(p, b, a, t, fb);
-                    gb[a] += additive ? g5[a] : g5[a] * (1.f + hh);
-                    const float gs = additive ? g5[a] : g5[a] * base[a];
-                    if (MREG > 0) {
-                        for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)fb[m], gd[a][m]);
-                    } else if (p.basis != SB_BASIS_STATIC) {
-                        for (int m = 0; m < p.M; ++m)
-                            unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b,
-                                            gs * eval_dH(p, b, a, m, t, fb));
+                if (MREG == 0 && p.d5) {
+                    float* const dst = p.d5 + sc.d5_0 + (int64_t)f * 5 * sc.n_balls + (b - sc.ball0);
+                    for (int a = 0; a < 5; ++a) global_atomic_add(dst + (int64_t)a * sc.n_balls, g5[a]);
+                } else {
+                    float base[5];
+                    for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
+                    for (int a = 0; a < 5; ++a) {
+                        const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
+                        const float hh = (float)eval_H(p, b, a, t, fb);
+                        gb[a] += additive ? g5[a] : g5[a] * (1.f + hh);
+                        if (MREG > 0) {
+                            const float gs = additive ? g5[a] : g5[a] * base[a];
+                            for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)fb[m], gd[a][m]);
+                        }
                     }
                 }
             }
         }
-        if (valid) {
+        if (valid && !(MREG == 0 && p.d5)) {
             for (int a = 0; a < 5; ++a) {
-                unsafeAtomicAdd(p.grad_balls + (int64_t)a * p.B + b, gb[a]);
+                global_atomic_add(p.grad_balls + (int64_t)a * p.B + b, gb[a]);
                 if (MREG > 0)
                     for (int m = 0; m < MREG; ++m)
-                        unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b, gd[a][m]);
+                        global_atomic_add(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b, gd[a][m]);
             }
         }
     }
@@ -580,31 +582,33 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                 g5[3] *= -2.f * rho * inv_delta_f * cp;
                 g5[4] *= delta * 0.25f;
             }
-            // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame
+            // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame, or
+            // (two-phase) this split's share of dL/d(deformed attributes) to the scratch
             if (live) {
-                float base[5];
-                for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
-                for (int a = 0; a < 5; ++a) {
-                    const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
-                    const float hh = (float)eval_H(p, b, a, t, s_fb);
-                    gb[a] += additive ? g5[a] : g5[a] * (1.f + hh);
-                    const float gs = additive ? g5[a] : g5[a] * base[a];
-                    if (MREG > 0) {
-                        for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)s_fb[m], gd[a][m]);
-                    } else if (p.basis != SB_BASIS_STATIC) {
-                        for (int m = 0; m < p.M; ++m)
-                            unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b,
-                                            gs * eval_dH(p, b, a, m, t, s_fb));
+                if (MREG == 0 && p.d5) {
+                    float* const dst = p.d5 + sc.d5_0 + (int64_t)f * 5 * sc.n_balls + (b - sc.ball0);
+                    for (int a = 0; a < 5; ++a) global_atomic_add(dst + (int64_t)a * sc.n_balls, g5[a]);
+                } else {
+                    float base[5];
+                    for (int a = 0; a < 5; ++a) base[a] = p.balls[(int64_t)a * p.B + b];
+                    for (int a = 0; a < 5; ++a) {
+                        const bool additive = (a < 3 && p.pos_mode == SB_POS_ADD);
+                        const float hh = (float)eval_H(p, b, a, t, s_fb);
+                        gb[a] += additive ? g5[a] : g5[a] * (1.f + hh);
+                        if (MREG > 0) {
+                            const float gs = additive ? g5[a] : g5[a] * base[a];
+                            for (int m = 0; m < MREG; ++m) gd[a][m] = fmaf(gs, (float)s_fb[m], gd[a][m]);
+                        }
                     }
                 }
             }
         }
-        if (valid) {
+        if (valid && !(MREG == 0 && p.d5)) {
             for (int a = 0; a < 5; ++a) {
-                unsafeAtomicAdd(p.grad_balls + (int64_t)a * p.B + b, gb[a]);
+                global_atomic_add(p.grad_balls + (int64_t)a * p.B + b, gb[a]);
                 if (MREG > 0)
                     for (int m = 0; m < MREG; ++m)
-                        unsafeAtomicAdd(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b, gd[a][m]);
+                        global_atomic_add(p.grad_deform + ((int64_t)a * p.M + m) * p.B + b, gd[a][m]);
             }
         }
     }
@@ -639,6 +643,95 @@ static hipError_t launch_adj_m(const OpParams& p, hipStream_t st) {
     // register accumulators for the Fourier coefficients when they fit (K <= 2)
     const bool reg = p.basis == SB_BASIS_FOURIER && p.M == 4;
     return reg ? launch_adj_t<UROW, 4, OCC>(p, st) : launch_adj_t<UROW, 0, OCC>(p, st);
+}
+
+// Second phase of the two-phase chain rule: one thread per ball.  From the summed
+// derivatives of the loss with respect to the ball's deformed attributes at every frame
+// of its scene (OpParams::d5), the gradients of its base attributes (Eq. 1: dx_f/dx = 1
+// for an additive position, 1 + H otherwise) and of every deformation coefficient
+// (dattr_f/dcoef = dH/dcoef times 1 for an additive position, times the base attribute
+// otherwise; Fourier: cos 2 pi k t, sin 2 pi k t; Eq. 2: e_n, w_n e_n (t - theta_n) /
+// sigma_n^2, w_n e_n (t - theta_n)^2 / sigma_n^3 with e_n = exp(-(t - theta_n)^2 /
+// (2 sigma_n^2))), summed over the frames in FP64 and stored (each ball's entries are
+// written by its thread only).
+__global__ __launch_bounds__(256) void chain_rule_kernel(OpParams p) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p.B) return;
+    int i = 0;
+    while (i + 1 < p.n_scenes && p.scenes[i + 1].ball0 <= b) ++i;
+    const Scene& sc = p.scenes[i];
+    if (sc.n_frames <= 0 || b - sc.ball0 >= sc.n_balls) return;
+    const int64_t nb = sc.n_balls;
+    const float* const g = p.d5 + sc.d5_0 + (b - sc.ball0);
+    const int M = p.M, N = p.n_terms;
+    for (int a = 0; a < 5; ++a) {
+        const bool additive = a < 3 && p.pos_mode == SB_POS_ADD;
+        const double base = p.balls[(int64_t)a * p.B + b];
+        const float* const d = p.deform + (int64_t)a * M * p.B + b;
+        float* const gdef = p.grad_deform + (int64_t)a * M * p.B + b;
+        double gbase = 0.0;
+        if (p.basis == SB_BASIS_FOURIER) {
+            double acc[2 * SB_MAX_FOURIER];
+            for (int m = 0; m < M; ++m) acc[m] = 0.0;
+            for (int f = 0; f < sc.n_frames; ++f) {
+                const double ga = g[((int64_t)f * 5 + a) * nb];
+                if (ga == 0.0) continue;
+                double fb[2 * SB_MAX_FOURIER];
+                fourier_basis(p.frame_t[sc.frame0 + f], N, fb);
+                double h = 0.0;
+                for (int m = 0; m < M; ++m) h = fma((double)d[(int64_t)m * p.B], fb[m], h);
+                gbase += additive ? ga : ga * (1.0 + h);
+                const double gs = additive ? ga : ga * base;
+                for (int m = 0; m < M; ++m) acc[m] = fma(gs, fb[m], acc[m]);
+            }
+            for (int m = 0; m < M; ++m) gdef[(int64_t)m * p.B] = (float)acc[m];
+        } else {
+            // Eq. 2, one basis at a time: its three coefficients summed over the frames
+            // (dL/dbase needs H, the sum over all bases, at every frame: a first pass)
+            if (!additive) {
+                for (int f = 0; f < sc.n_frames; ++f) {
+                    const double ga = g[((int64_t)f * 5 + a) * nb];
+                    if (ga == 0.0) continue;
+                    gbase += ga * (1.0 + gauss_basis_H(d, p.B, N, p.frame_t[sc.frame0 + f]));
+                }
+            } else {
+                for (int f = 0; f < sc.n_frames; ++f) gbase += g[((int64_t)f * 5 + a) * nb];
+            }
+            for (int n = 0; n < N; ++n) {
+                const double w = d[(int64_t)(3 * n) * p.B];
+                const double th = d[(int64_t)(3 * n + 1) * p.B];
+                const double sg = d[(int64_t)(3 * n + 2) * p.B];
+                double aw = 0.0, at = 0.0, as = 0.0;
+                for (int f = 0; f < sc.n_frames; ++f) {
+                    const double ga = g[((int64_t)f * 5 + a) * nb];
+                    if (ga == 0.0) continue;
+                    const double gs = additive ? ga : ga * base;
+                    const double dt = (double)p.frame_t[sc.frame0 + f] - th;
+                    const double e = exp(-dt * dt / (2.0 * sg * sg));
+                    aw = fma(gs, e, aw);
+                    at = fma(gs, w * e * dt / (sg * sg), at);
+                    as = fma(gs, w * e * dt * dt / (sg * sg * sg), as);
+                }
+                gdef[(int64_t)(3 * n) * p.B] = (float)aw;
+                gdef[(int64_t)(3 * n + 1) * p.B] = (float)at;
+                gdef[(int64_t)(3 * n + 2) * p.B] = (float)as;
+            }
+        }
+        p.grad_balls[(int64_t)a * p.B + b] = (float)gbase;
+    }
+}
+
+hipError_t launch_chain_rule(const OpParams& p, hipStream_t st) {
+    if (p.B <= 0) return hipSuccess;
+    const int64_t blocks = (p.B + 255) / 256;
+    hipLaunchKernelGGL(chain_rule_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+// Deformed bases whose coefficients the adjoint kernels do not keep in registers (all
+// but the 2-harmonic Fourier series) take the two-phase chain rule.
+bool adjoint_two_phase(const OpParams& p) {
+    return p.basis != SB_BASIS_STATIC && !(p.basis == SB_BASIS_FOURIER && p.M == 4);
 }
 
 // tc.ucap: residual row length; tc.nw: blocks per CU requested from the compiler (occupancy)

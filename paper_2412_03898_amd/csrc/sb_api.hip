@@ -27,13 +27,16 @@ static int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-// Per-device scratch: the sticky flag word, the loss partials, and the
-// ordering buffers (grown on demand, kept until the process ends).
+// Per-device scratch: the sticky flag word, the loss partials, the ordering
+// buffers and the adjoint's two-phase chain-rule buffer (grown on demand, kept
+// until the process ends).
 struct DeviceState {
     unsigned* flags = nullptr;
     double* partials = nullptr;
     void* order_buf = nullptr;
     size_t order_bytes = 0;
+    float* d5 = nullptr;
+    size_t d5_bytes = 0;
 };
 
 static std::mutex g_mu;
@@ -223,6 +226,12 @@ static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batc
         s.n_groups = (s.n_balls + 255) / 256;
         if (s.n_frames > 0) chunks += s.n_groups;
     }
+    int64_t d5 = 0;          // two-phase chain rule: [frame][5][ball] per scene, concatenated
+    for (int i = 0; i < batch->n_scenes; ++i) {
+        Scene& s = p.scenes[i];
+        s.d5_0 = d5;
+        d5 += (int64_t)s.n_frames * 5 * s.n_balls;
+    }
     const int64_t target = tu.adj_items;
     int64_t n_split = chunks > 0 ? (target + chunks - 1) / chunks : 1;
     const int64_t max_split = sh.S >= 8 ? sh.S / 8 : 1;
@@ -243,6 +252,46 @@ static void fill_adjoint(OpParams& p, const sb_config* cfg, const sb_batch* batc
 
 static int hip_fail(hipError_t e, const char* what) {
     return fail(SB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Floats of the adjoint's two-phase chain-rule buffer for this problem (0: the
+// kernels apply the chain rule themselves).
+static int64_t d5_floats(const sb_config* cfg, const sb_batch* batch, const Shape& sh) {
+    OpParams q;
+    memset(&q, 0, sizeof q);
+    q.basis = cfg->basis;
+    q.M = sh.M;
+    if (!adjoint_two_phase(q)) return 0;
+    int64_t n = 0;
+    for (int i = 0; i < batch->n_scenes; ++i)
+        n += (batch->frame_offset[i + 1] - batch->frame_offset[i]) * 5 *
+             (batch->ball_offset[i + 1] - batch->ball_offset[i]);
+    return n;
+}
+
+// Grows the per-device chain-rule buffer to `floats` entries.  Growing waits for
+// `stream` (the old buffer may still be read) and allocates, so it cannot happen
+// under graph capture: slingbag_plan_create reserves the buffer before capturing.
+static int reserve_d5(DeviceState* ds, int64_t floats, hipStream_t s) {
+    const size_t need = (size_t)floats * sizeof(float);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (ds->d5_bytes >= need) return SB_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(SB_ERR_INVALID_ARG, "the adjoint's chain-rule buffer (%zu bytes) must be reserved before "
+                    "graph capture (slingbag_plan_create does)", need);
+    hipError_t e = hipSuccess;
+    if (ds->d5) {
+        e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = hipFree(ds->d5);
+        if (e != hipSuccess) return hip_fail(e, "release chain-rule buffer");
+        ds->d5 = nullptr;
+        ds->d5_bytes = 0;
+    }
+    e = hipMalloc(&ds->d5, need);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(chain-rule buffer)");
+    ds->d5_bytes = need;
+    return SB_OK;
 }
 
 // Opt-in event timing of the main kernel launches (slingbag_timing).  Each
@@ -435,8 +484,16 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* b
     p.grad_balls = grad_balls;
     p.grad_deform = grad_deform;
     p.flags = ds->flags;
+    const int64_t n5 = d5_floats(cfg, batch, sh);
+    if (n5 > 0) {
+        if ((st = reserve_d5(ds, n5, s))) return st;
+        p.d5 = ds->d5;
+        e = launch_fill(p.d5, n5, 0.f, s);
+        if (e != hipSuccess) return hip_fail(e, "fill(chain-rule buffer)");
+    }
     time_mark(kTimeAdjoint, 0, s);
     e = launch_adjoint(p, tc, cfg->kernel, s);
+    if (e == hipSuccess && p.d5) e = launch_chain_rule(p, s);
     time_mark(kTimeAdjoint, 1, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
     return SB_OK;
@@ -812,6 +869,8 @@ int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const floa
     DeviceState* ds;
     if ((st = device_state(&ds))) return st;   // per-device buffers exist before capture
     hipStream_t s = (hipStream_t)stream;
+    const int64_t n5 = d5_floats(cfg, batch, sh);
+    if (n5 > 0 && (st = reserve_d5(ds, n5, s))) return st;
     // with timing on, the timed launches are captured between event record nodes
     CaptureTiming tm;
     const bool timed = g_timing.enabled;

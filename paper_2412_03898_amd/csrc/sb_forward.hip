@@ -262,7 +262,7 @@ __device__ inline bool add_window_global(float* row, int klo, int T, int W, floa
         }
         const int k = klo + j;
         if (v != 0.f) {
-            if (k >= 0 && k < T) unsafeAtomicAdd(row + k, v);
+            if (k >= 0 && k < T) global_atomic_add(row + k, v);
             else clipped = true;
         }
     }
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                                 const uint64_t pa =
                                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(rowp >> 32), a) << 32) |
                                     (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rowp, a);
-                                if (v[u] != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(pa) + (q * 64 + lane), v[u]);
+                                if (v[u] != 0.f) global_atomic_add(reinterpret_cast<float*>(pa) + (q * 64 + lane), v[u]);
                             }
                         }
                     } else {
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                                 const int64_t ra = ((int64_t)__builtin_amdgcn_readlane((int)(row_off >> 32), a) << 32) |
                                                    (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)row_off, a);
                                 if (v[u] != 0.f && act_a) {
-                                    if (k >= 0 && k < p.T) unsafeAtomicAdd(p.signals + ra + k, v[u]);
+                                    if (k >= 0 && k < p.T) global_atomic_add(p.signals + ra + k, v[u]);
                                     else clipped = true;
                                 }
                             }

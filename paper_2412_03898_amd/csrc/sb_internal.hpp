@@ -19,6 +19,7 @@ struct Scene {
     int32_t frame0;     // first frame (global index)
     int32_t n_frames;
     int32_t n_groups;   // ceil(n_balls / G)
+    int64_t d5_0;       // adjoint, two-phase chain rule: first entry of this scene in OpParams::d5
 };
 
 // Kernel argument block (passed by value).
@@ -32,6 +33,12 @@ struct OpParams {
     float* grad_balls;       // [5][B]
     float* grad_deform;      // [5][M][B]
     unsigned* flags;         // device flag word
+    // Adjoint with a two-phase chain rule (deformed bases with more coefficients than
+    // the kernels keep in registers): per scene, [frame][5][ball] derivatives of the loss
+    // with respect to the deformed attributes, summed over the sensor splits by the
+    // adjoint kernels and turned into parameter gradients by chain_rule_kernel.  Null:
+    // the adjoint kernels apply the chain rule themselves.
+    float* d5;
     int64_t B;               // total balls (row stride of balls/deform)
     int64_t n_items;
     double inv_delta;        // fs / c   (samples per metre)
@@ -149,21 +156,6 @@ __device__ inline double eval_H(const OpParams& p, int64_t b, int a, float t, co
     return h;
 }
 
-// dH/d(coefficient m) of attribute a of ball b at time t.
-__device__ inline float eval_dH(const OpParams& p, int64_t b, int a, int m, float t, const double* fb) {
-    if (p.basis == SB_BASIS_FOURIER) return (float)fb[m];
-    const float* d = p.deform + (int64_t)a * p.M * p.B + b;
-    int n = m / 3, which = m - 3 * n;
-    float w = d[(int64_t)(3 * n) * p.B];
-    float th = d[(int64_t)(3 * n + 1) * p.B];
-    float sg = d[(int64_t)(3 * n + 2) * p.B];
-    float dt = t - th;
-    float e = expf(-dt * dt / (2.f * sg * sg));
-    if (which == 0) return e;
-    if (which == 1) return w * e * dt / (sg * sg);
-    return w * e * dt * dt / (sg * sg * sg);
-}
-
 // Deformed attributes (Eq. 1) of ball b at time t; positions and size in FP64.
 // Returns false (and marks the ball to skip) for invalid attributes.
 __device__ inline bool deform_ball(const OpParams& p, int64_t b, float t, const double* fb,
@@ -187,6 +179,16 @@ __device__ inline bool deform_ball(const OpParams& p, int64_t b, float t, const 
     out.rhof = (float)out.rho;
     out.amp = ok ? (float)Pf : 0.f;
     return ok;
+}
+
+// FP32 atomic add to global memory, as an instruction the compiler knows to be a
+// global one.  An address rebuilt from lane reads is otherwise generic, which makes
+// the atomic a FLAT operation; FLAT operations count on the same wait counter as
+// LDS operations and may complete out of their order, so after one the compiler can
+// only wait for every outstanding LDS operation at once.
+__device__ inline void global_atomic_add(float* p, float v) {
+    (void)__builtin_amdgcn_global_atomic_fadd_f32(
+        (__attribute__((address_space(1))) float*)(p), v);
 }
 
 __device__ inline void raise_flag(unsigned* flags, unsigned bit) {
@@ -316,6 +318,8 @@ struct TileCfg {
 
 hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st);
 hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st);
+bool adjoint_two_phase(const OpParams& p);     // does launch_adjoint need OpParams::d5?
+hipError_t launch_chain_rule(const OpParams& p, hipStream_t st);
 hipError_t launch_morton_keys(const float* balls, int64_t B, const int64_t* ball_offset_host,
                               int n_scenes, unsigned long long* keys, int* idx, hipStream_t st);
 hipError_t sort_pairs(void* temp, size_t& temp_bytes, const unsigned long long* kin,

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void voxelize_kernel(OpParams p, GridP g, floa
             const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
             if (d2 <= reach2) {
                 const float val = (KERNEL == SB_KERNEL_UNIFORM) ? amp : amp * __expf((float)d2 * ce);
-                unsafeAtomicAdd(vol + ((int64_t)k * g.ny + j) * g.nx + i, val);
+                global_atomic_add(vol + ((int64_t)k * g.ny + j) * g.nx + i, val);
             }
         }
     }

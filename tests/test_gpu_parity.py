@@ -146,6 +146,14 @@ VARIANTS = [
     dict(kernel=1, basis=0),
     dict(kernel=1, basis=1),
     dict(kernel=1, basis=2, pos_mode=1),
+    # the two-phase chain rule: Fourier series beyond 2 harmonics, and Eq. 2 with 13 and
+    # 65 bases per attribute (the two readings of the 65 Gaussian basis functions)
+    dict(basis=1, K=3),
+    dict(kernel=1, basis=1, K=5, pos_mode=1),
+    dict(basis=2, pos_mode=1, N=13),
+    dict(basis=2, pos_mode=1, N=65),
+    dict(kernel=1, basis=2, pos_mode=1, N=13),
+    dict(kernel=1, basis=2, pos_mode=0, N=65),
 ]
 
 

@@ -61,7 +61,9 @@ def _fwd(cfg, batch, balls=None, deform=None, frame_t=None, sensors=None, signal
     (dict(pos_mode=-1), binding.SB_ERR_INVALID_ARG, "pos_mode"),
     (dict(basis=1, n_terms=0), binding.SB_ERR_SHAPE, "n_terms"),
     (dict(basis=1, n_terms=9), binding.SB_ERR_SHAPE, "n_terms"),
-    (dict(basis=2, n_terms=17), binding.SB_ERR_SHAPE, "n_terms"),
+    (dict(basis=2, n_terms=129), binding.SB_ERR_SHAPE, "n_terms"),
+    # 65 bases per attribute pass the model checks and stop at the missing device pointers
+    (dict(basis=2, n_terms=65), binding.SB_ERR_INVALID_ARG, "is NULL"),
     (dict(n_sensors=0), binding.SB_ERR_SHAPE, "n_sensors"),
     (dict(n_samples=0), binding.SB_ERR_SHAPE, "n_samples"),
     (dict(n_samples=(1 << 28) + 1), binding.SB_ERR_SHAPE, "n_samples"),

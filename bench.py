@@ -30,7 +30,9 @@ forward + adjoint (GPairs/s); `ms_per_step` the IR iteration.  Beside it:
                 on one frame x every 32nd sensor of the same scene, with the
                 GPU's outputs on exactly those rows checked against it;
   extras        the single-frame vessel scene, the small 4D scene (batched vs
-                frame by frame), the uneven 8-scene batch and the voxel grid.
+                frame by frame), the uneven 8-scene batch, the small 4D scene with
+                N = 1, 4, 13, 65 Gaussian bases per attribute (Eq. 2), and the
+                voxel grid.
 """
 
 from __future__ import annotations
@@ -193,7 +195,12 @@ def setup_scene(wl, tuning=None):
         gt = (balls.cpu().numpy(), deform.cpu().numpy())
         del balls
         balls = start
-        deform = torch.zeros_like(deform)
+        if wl.basis == 2:
+            # Eq. 2 from H = 0: every weight zero, the centres and widths kept
+            deform = deform.clone()
+            deform[:, 0::3] = 0.0
+        else:
+            deform = torch.zeros_like(deform)
     else:
         pert = torch.from_numpy(synth.perturbed(balls.cpu().numpy(), 1)).cuda()
         measured = ops.forward(pb, pert, None, ft, sens)
@@ -377,6 +384,23 @@ def scene_step(wl, steps, warmup, tuning=None, compare_per_frame=False):
     return rec
 
 
+def basis_sweep(counts=(1, 4, 13, 65), steps=6, warmup=1):
+    """ms per IR iteration of the small 4D scene (50,000 balls, 16 frames, 512 sensors,
+    2,048 samples) with the Gaussian-basis deformation of Eq. 2 (additive position) at N
+    bases per attribute, against the 2-harmonic Fourier series of the same scene."""
+    import dataclasses
+    from paper_2412_03898_amd import synth
+    base = synth.workload_vessel_4d()
+    out = {}
+    for n in counts:
+        wl = dataclasses.replace(base, basis=2, n_terms=n,
+                                 deform=synth.gauss_basis_coeffs(base.n_balls, n, 5))
+        r = scene_step(wl, steps, warmup)
+        out[str(n)] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"], "tuning": r["tuning"],
+                       "coefficients_per_ball": 15 * n}
+    return out
+
+
 def voxel_map_timing(reps=5):
     """Point cloud -> voxel grid -> maximum amplitude projections: the single-frame vessel
     scene (200,000 balls) on a 40 mm cube of 0.1 mm voxels (400^3, 256 MB); mean ms of
@@ -516,6 +540,7 @@ def main():
         if args.workload != "vessel-4d":
             ex["small_4d"] = scene_step(synth.workload_vessel_4d(), 12, 2, compare_per_frame=True)
         ex["uneven_batch"] = scene_step(synth.workload_uneven_batch(), 4, 1)
+        ex["gauss_basis_sweep_small_4d"] = basis_sweep()
         ex["voxel_map"] = voxel_map_timing()
         out["extras"] = ex
     print(json.dumps(out), flush=True)

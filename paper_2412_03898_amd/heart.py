@@ -7,9 +7,10 @@ multiplicative positions as in Eq. 1) start at H = 0 (every weight zero), and al
 frames are fitted together.  The cloud is made of Gaussian balls (Sec. 2.1)
 initialised on a regular grid over the phantom's region with a small pressure.
 
-Quality is reported as the Pearson correlation between the XY maximum amplitude
-projections of the reconstruction and of the ground truth at every frame (the
-paper shows these images for this experiment and prints no numbers for it).
+Quality is reported as the Pearson correlation between the maximum amplitude
+projections (XY, YZ and XZ) of the reconstruction and of the ground truth at every
+frame (the paper shows these images for this experiment and prints no numbers for
+it), after stage 1 and at chosen iteration counts of stage 2.
 
 `python -m paper_2412_03898_amd.heart` runs it at full size (1,024 sensors on the
 60 mm sphere, 17 frames) and prints one JSON line.
@@ -66,14 +67,16 @@ def _pearson(a, b) -> float:
     return float((a * b).sum()) / den if den > 0 else 0.0
 
 
-def map_correlation(gt, recon_pb, recon_balls, recon_deform, frame_t, grid) -> list[float]:
-    """Per-frame Pearson correlation of the XY MAPs of ground truth and reconstruction."""
+def map_correlation(gt, recon_pb, recon_balls, recon_deform, frame_t, grid) -> dict:
+    """Per-frame Pearson correlation of the XY, YZ and XZ MAPs of ground truth and
+    reconstruction: {"xy": [F], "yz": [F], "xz": [F]}."""
     (pb_s, bs, ds), (pb_e, be, de) = gt
-    out = []
+    out = {"xy": [], "yz": [], "xz": []}
     for t in frame_t.tolist():
         v_gt = ops.voxelize(pb_s, bs, ds, t, grid) + ops.voxelize(pb_e, be, de, t, grid)
         v_re = ops.voxelize(recon_pb, recon_balls, recon_deform, t, grid)
-        out.append(_pearson(ops.map_projections(v_gt)[0], ops.map_projections(v_re)[0]))
+        for name, a, b in zip(("xy", "yz", "xz"), ops.map_projections(v_gt), ops.map_projections(v_re)):
+            out[name].append(round(_pearson(a, b), 4))
     ops.check()
     return out
 
@@ -81,23 +84,28 @@ def map_correlation(gt, recon_pb, recon_balls, recon_deform, frame_t, grid) -> l
 def two_stage(n_static: int = 200, n_4d: int = 200, n_sensors: int = 1024, n_frames: int = 17,
               fit_half: float = 13e-3, fit_spacing: float = 1.0e-3, fit_std: float = 0.3e-3,
               p0: float = 0.02, lr_scale: float = 1.0, seed: int = 31, phantom_spacing: float = 0.5e-3,
-              voxel: float = 0.25e-3, log=print) -> dict:
+              voxel: float = 0.25e-3, n_bases: int = N_BASES, report_at=(), deform_lr_scale: float = 1.0,
+              decay_step: int | None = None, log=print) -> dict:
     """The two-stage reconstruction of the heart phantom; returns the result record.  The
-    kernel knobs are autotuned per stage and restored afterwards."""
+    kernel knobs are autotuned per stage and restored afterwards.  `report_at`: stage-2
+    iteration counts (below n_4d) at which the MAP correlations are also recorded.
+    `deform_lr_scale` multiplies the deformation coefficients' learning rate on top of
+    `lr_scale`."""
     from . import binding
     keys = (binding.SB_TUNE_FWD_COLUMN, binding.SB_TUNE_ADJ_OCCUPANCY, binding.SB_TUNE_ADJ_ITEMS,
             binding.SB_TUNE_FWD_GAUSS_COLUMN)
     saved = [binding.tune_get(k) for k in keys]
     try:
         return _two_stage(n_static, n_4d, n_sensors, n_frames, fit_half, fit_spacing, fit_std, p0,
-                          lr_scale, seed, phantom_spacing, voxel, log)
+                          lr_scale, seed, phantom_spacing, voxel, n_bases, report_at, deform_lr_scale,
+                          decay_step, log)
     finally:
         for k, v in zip(keys, saved):
             binding.tune(k, v)
 
 
 def _two_stage(n_static, n_4d, n_sensors, n_frames, fit_half, fit_spacing, fit_std, p0, lr_scale, seed,
-               phantom_spacing, voxel, log) -> dict:
+               phantom_spacing, voxel, n_bases, report_at, deform_lr_scale, decay_step, log) -> dict:
     t_start = time.perf_counter()
     slabs, ell = synth.heart_phantom(n_sensors=n_sensors, n_frames=n_frames, spacing=phantom_spacing)
     pb_s, bs, _, ft, sens = ops.to_device(slabs)
@@ -109,7 +117,7 @@ def _two_stage(n_static, n_4d, n_sensors, n_frames, fit_half, fit_spacing, fit_s
     F = n_frames
     rng = np.random.default_rng(seed)
     f_ref = int(rng.integers(F))
-    lrs = (LR_POS * lr_scale, LR_R * lr_scale, LR_P * lr_scale, LR_DEF * lr_scale)
+    lrs = (LR_POS * lr_scale, LR_R * lr_scale, LR_P * lr_scale, LR_DEF * lr_scale * deform_lr_scale)
 
     # ---- stage 1: static reconstruction of the reference frame
     cloud = torch.from_numpy(init_cloud(fit_half, fit_spacing, fit_std, p0, seed)).cuda()
@@ -121,33 +129,47 @@ def _two_stage(n_static, n_4d, n_sensors, n_frames, fit_half, fit_spacing, fit_s
     # kernel knobs timed on each stage's own shapes (the 4D stage's Eq. 2 chain rule per work
     # item wants fewer, larger sensor splits than a static frame)
     tuning1 = tune.autotune(pb1, cloud, None, ft1, sens, cache=None)
-    s1 = IRLoop(pb1, cloud, None, ft1, sens, m1, lrs=lrs)
+    s1 = IRLoop(pb1, cloud, None, ft1, sens, m1, lrs=lrs[:3] + (LR_DEF,))
     l1 = s1.run(n_static)
     s1.close()
     log(f"[heart] stage 1 (frame {f_ref}, {B} balls): loss {l1[0]:.4e} -> {l1[-1]:.4e}")
 
     # ---- stage 2: 4D with the Gaussian-basis deformation from H = 0
-    deform = torch.from_numpy(gauss_basis_start(B)).cuda()
-    pb2 = _problem(slabs, 1, 2, 1, N_BASES, B, F)
+    deform = torch.from_numpy(gauss_basis_start(B, n_bases)).cuda()
+    pb2 = _problem(slabs, 1, 2, 1, n_bases, B, F)
     tuning2 = tune.autotune(pb2, cloud, deform, ft, sens, cache=None)
-    s2 = IRLoop(pb2, cloud, deform, ft, sens, measured, lrs=lrs)
+    kw = {} if decay_step is None else {"decay_step": decay_step}
+    s2 = IRLoop(pb2, cloud, deform, ft, sens, measured, lrs=lrs, **kw)
     L_start = s2.full_loss()
     n_grid = int(round(2 * 24e-3 / voxel))
     grid = (n_grid, n_grid, n_grid, -24e-3 + voxel / 2, -24e-3 + voxel / 2, -24e-3 + voxel / 2, voxel)
     gt = ((pb_s, bs, None), (pb_e, be, de))
-    corr0 = map_correlation(gt, pb2, cloud, deform, ft, grid)
-    l2 = s2.run(n_4d)
+    corr = {0: map_correlation(gt, pb2, cloud, deform, ft, grid)}     # after stage 1
+    done, t_iter = 0, 0.0
+    for stop in sorted({int(n) for n in report_at if 0 < int(n) < n_4d} | {n_4d}):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s2.run(stop - done)
+        torch.cuda.synchronize()
+        t_iter += time.perf_counter() - t
+        done = stop
+        corr[stop] = map_correlation(gt, pb2, cloud, deform, ft, grid)
     L_end = s2.full_loss()
     s2.close()
-    corr1 = map_correlation(gt, pb2, cloud, deform, ft, grid)
-    log(f"[heart] stage 2 (4D, {F} frames): loss {L_start:.4e} -> {L_end:.4e}; "
-        f"XY-MAP correlation {np.mean(corr0):.3f} -> {np.mean(corr1):.3f}")
+    c0, c1 = corr[0], corr[n_4d]
+    log(f"[heart] stage 2 (4D, {F} frames, {n_bases} bases per attribute): loss {L_start:.4e} -> {L_end:.4e}; "
+        f"XY-MAP correlation {np.mean(c0['xy']):.3f} -> {np.mean(c1['xy']):.3f}")
+    worse = {k: [f for f in range(F) if c1[k][f] < c0[k][f]] for k in c0}
     return {"workload": "heart-phantom", "sensors": n_sensors, "frames": F, "samples": slabs.n_samples,
             "gt_balls": [slabs.n_balls, ell.n_balls], "fit_balls": B, "reference_frame": f_ref,
+            "bases_per_attribute": n_bases,
             "stage1_iters": n_static, "stage1_loss": [l1[0], l1[-1]],
             "stage2_iters": n_4d, "stage2_loss_all_frames": [L_start, L_end],
-            "xy_map_corr_start": [round(c, 4) for c in corr0], "xy_map_corr_end": [round(c, 4) for c in corr1],
-            "lr_scale": lr_scale, "tuning": {"stage1": list(tuning1), "stage2": list(tuning2)},
+            "stage2_ms_per_iter": round(t_iter / max(n_4d, 1) * 1e3, 2),
+            "map_corr": {str(k): v for k, v in corr.items()},
+            "frames_below_stage1": worse,
+            "lr_scale": lr_scale, "deform_lr_scale": deform_lr_scale,
+            "decay_step": decay_step if decay_step is not None else 160, "tuning": {"stage1": list(tuning1), "stage2": list(tuning2)},
             "seconds": round(time.perf_counter() - t_start, 1)}
 
 
@@ -156,8 +178,18 @@ def main():
     ap.add_argument("--static-iters", type=int, default=200)
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--lr-scale", type=float, default=1.0, help="multiply the paper's learning rates")
+    ap.add_argument("--deform-lr-scale", type=float, default=1.0,
+                    help="further multiply the deformation coefficients' learning rate")
+    ap.add_argument("--decay-step", type=int, default=None, help="iterations per x0.1 learning-rate step "
+                    "(default: the paper's 160)")
+    ap.add_argument("--bases", type=int, default=N_BASES, help="Gaussian bases per attribute (Eq. 2)")
+    ap.add_argument("--report-at", default="", help="comma-separated stage-2 iteration counts at which "
+                    "the MAP correlations are also recorded")
     args = ap.parse_args()
-    rec = two_stage(args.static_iters, args.iters, lr_scale=args.lr_scale, log=lambda s: print(s, flush=True))
+    report = [int(x) for x in args.report_at.split(",") if x]
+    rec = two_stage(args.static_iters, args.iters, lr_scale=args.lr_scale, n_bases=args.bases, report_at=report,
+                    deform_lr_scale=args.deform_lr_scale, decay_step=args.decay_step,
+                    log=lambda s: print(s, flush=True))
     print(json.dumps(rec), flush=True)
 
 

@@ -18,4 +18,5 @@ def test_two_stage_small():
     a, b = rec["stage1_loss"]
     c, d = rec["stage2_loss_all_frames"]
     assert b < a and d < c
-    assert np.all(np.isfinite(rec["xy_map_corr_end"]))
+    for plane in ("xy", "yz", "xz"):
+        assert np.all(np.isfinite(rec["map_corr"]["25"][plane]))

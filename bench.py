@@ -332,6 +332,17 @@ def roofline(wl, balls_np, deform_np, kt, choice):
         gbs = traffic / sec / 1e9
         out["hbm"] = {"achieved_gb_s": round(gbs, 1), "peak_gb_s": HBM_PEAK_GBS,
                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    # the other kernel of the pass, for context
+    other = "adjoint" if dom == "forward" else "forward"
+    if per[other]:
+        osec = per[other] * 1e-3
+        t2, q2 = sq_and_traffic(kernel_instance(other, wl, choice), wl.name)
+        out["other_kernel"] = {
+            "kernel": other, "kernel_ms": round(per[other], 3),
+            "frac": round(fm[other] / osec / 1e12 / ALU_PEAK_TOPS, 4),
+            "issued_valu_frac": None if q2 is None else round(q2 * 64 / osec / 1e12 / ALU_PEAK_TOPS, 4),
+            "traffic": t2,
+            "hbm_frac": None if t2 is None else round(t2 / osec / 1e9 / HBM_PEAK_GBS, 4)}
     return out, per
 
 

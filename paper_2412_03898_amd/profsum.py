@@ -6,6 +6,7 @@ usage:
 
   python -m paper_2412_03898_amd.profsum traffic <out.json> <kernel> <workload> <fetch.csv> <write.csv> <fetch_scale> <write_scale> <fetch_cmd> <write_cmd> <source>...
   python -m paper_2412_03898_amd.profsum sq <out.json> <kernel> <workload> <counter.csv> <cmd> <source>...
+  (traffic and sq take an optional first argument --skip=K: leave out the kernel's first K dispatches)
 
 `traffic` records the HBM bytes per dispatch of one kernel (dispatches whose name
 contains <kernel>), scaled by the copy-calibration factors, together with a
@@ -78,11 +79,18 @@ def counters(out, title, note, pairs):
         f.write("\n".join(lines) + "\n")
 
 
+def _dispatch_values(path, kernel, counter, skip):
+    """Values of `counter` for the dispatches of `kernel` in dispatch order, without the
+    first `skip` of them (for instance a launch that prepares the measured data)."""
+    rows = [r for r in csv.DictReader(open(path)) if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in rows[skip:]]
+
+
 def traffic(out, kernel, workload, fetch_csv, write_csv, fetch_scale, write_scale, fetch_cmd, write_cmd,
-            sources):
+            sources, skip=0):
     def mean(path, counter):
-        v = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
-             if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        v = _dispatch_values(path, kernel, counter, skip)
         if not v:
             raise SystemExit(f"no {counter} dispatch of {kernel} in {path}")
         return sum(v) / len(v), len(v)
@@ -91,23 +99,23 @@ def traffic(out, kernel, workload, fetch_csv, write_csv, fetch_scale, write_scal
     rec = {"kernel": kernel, "workload": workload, "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
            "dispatches": [nf, nw], "fetch_scale": float(fetch_scale), "write_scale": float(write_scale),
            "bytes_per_launch": round(float(fetch_scale) * fk * 1024 + float(write_scale) * wk * 1024),
+           "skipped_first_dispatches": skip,
            "commands": [fetch_cmd, write_cmd], "sources": sources, "source_sha256": source_digest(sources)}
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
 
 
-def sq(out, kernel, workload, csv_path, command, sources):
-    agg = collections.defaultdict(list)
-    for r in csv.DictReader(open(csv_path)):
-        if kernel in r["Kernel_Name"]:
-            agg[r["Counter_Name"]].append(float(r["Counter_Value"]))
+def sq(out, kernel, workload, csv_path, command, sources, skip=0):
+    names = sorted({r["Counter_Name"] for r in csv.DictReader(open(csv_path)) if kernel in r["Kernel_Name"]})
+    agg = {c: _dispatch_values(csv_path, kernel, c, skip) for c in names}
+    agg = {c: v for c, v in agg.items() if v}
     if not agg:
         raise SystemExit(f"no dispatch of {kernel} in {csv_path}")
     rec = {"kernel": kernel, "workload": workload,
            "counters": {k: round(sum(v) / len(v), 1) for k, v in sorted(agg.items())},
-           "dispatches": max(len(v) for v in agg.values()), "command": command, "sources": sources,
-           "source_sha256": source_digest(sources)}
+           "dispatches": max(len(v) for v in agg.values()), "skipped_first_dispatches": skip,
+           "command": command, "sources": sources, "source_sha256": source_digest(sources)}
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
@@ -154,12 +162,16 @@ def main():
         out, title, note = sys.argv[2:5]
         rest = sys.argv[5:]
         counters(out, title, note, list(zip(rest[0::2], rest[1::2])))
-    elif mode == "traffic":
+    elif mode in ("traffic", "sq"):
         a = sys.argv[2:]
-        traffic(*a[:9], sources=a[9:])
-    elif mode == "sq":
-        a = sys.argv[2:]
-        sq(*a[:5], sources=a[5:])
+        skip = 0
+        if a and a[0].startswith("--skip="):
+            skip = int(a[0].split("=", 1)[1])
+            a = a[1:]
+        if mode == "traffic":
+            traffic(*a[:9], sources=a[9:], skip=skip)
+        else:
+            sq(*a[:5], sources=a[5:], skip=skip)
     else:
         raise SystemExit(__doc__)
 

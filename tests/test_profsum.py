@@ -44,10 +44,15 @@ def test_sq_record_follows_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(profsum, "ROOT", str(root))
     monkeypatch.setattr(profsum, "PROFILES", str(root / "profiles"))
     csv_path = root / "pmc.csv"
-    csv_path.write_text("Kernel_Name,Counter_Name,Counter_Value\n"
-                        "void sb::k<1>(x),SQ_INSTS_VALU,100\nvoid sb::k<1>(x),SQ_INSTS_VALU,300\n"
-                        "void sb::k<1>(x),SQ_WAVES,8\nvoid sb::other(x),SQ_INSTS_VALU,5\n")
+    csv_path.write_text("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+                        "3,void sb::k<1>(x),SQ_INSTS_VALU,100\n5,void sb::k<1>(x),SQ_INSTS_VALU,300\n"
+                        "1,void sb::k<1>(x),SQ_INSTS_VALU,7000\n"
+                        "3,void sb::k<1>(x),SQ_WAVES,8\n5,void sb::k<1>(x),SQ_WAVES,8\n1,void sb::k<1>(x),SQ_WAVES,8\n"
+                        "2,void sb::other(x),SQ_INSTS_VALU,5\n")
     profsum.sq(str(root / "profiles" / "k_w_sq.json"), "k<1>", "w", str(csv_path), "cmd", ["k.hip"])
+    assert profsum.sq_for("k<1>", "w") == 2466.7          # (100 + 300 + 7000) / 3, rounded
+    # the first dispatch (in dispatch order, not file order) left out
+    profsum.sq(str(root / "profiles" / "k_w_sq.json"), "k<1>", "w", str(csv_path), "cmd", ["k.hip"], skip=1)
     assert profsum.sq_for("k<1>", "w") == 200.0
     assert profsum.sq_for("k<1>", "w", "SQ_WAVES") == 8.0
     assert profsum.sq_for("k<1>", "other") is None

@@ -170,9 +170,10 @@ int slingbag_loss_noalloc(const sb_config* cfg, const sb_batch* batch,
  * 2-harmonic Fourier series (and STATIC) apply the chain rule inside the
  * adjoint kernel; every other basis sums the derivatives with respect to each
  * ball's deformed attributes at every frame (5 floats per ball and frame) in a
- * per-device buffer, allocated on first use and grown as needed (not under
- * graph capture: slingbag_plan_create reserves it), and applies the chain rule
- * once per ball in a second kernel. */
+ * per-device buffer, allocated on first use and grown as needed (growing
+ * cannot happen under graph capture: call slingbag_adjoint once on the problem
+ * before capturing it), and applies the chain rule once per ball in a second
+ * kernel.  A plan allocates a buffer of its own (see slingbag_plan_create). */
 int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch,
                      const float* balls, const float* deform, const float* frame_t,
                      const float* sensors, const float* residual,
@@ -228,8 +229,10 @@ int slingbag_check(void* stream, uint32_t* flags);
  * plan created while timing is on (slingbag_timing) also records an event
  * node before and after its forward, loss and adjoint kernels, and every
  * replay while timing is on times them into the same pool as direct calls.
- * The plan owns the graph (and those nodes' own events);
- * slingbag_plan_destroy releases them (NULL is a no-op). */
+ * The plan owns the graph, those nodes' own events and, for deformations that
+ * take the adjoint's two-phase chain rule, its own chain-rule buffer (5 floats
+ * per ball and frame, allocated at creation); slingbag_plan_destroy releases
+ * them (NULL is a no-op). */
 typedef struct sb_plan sb_plan;
 int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const float* balls,
                          const float* deform, const float* frame_t, const float* sensors,

@@ -271,15 +271,15 @@ static int64_t d5_floats(const sb_config* cfg, const sb_batch* batch, const Shap
 
 // Grows the per-device chain-rule buffer to `floats` entries.  Growing waits for
 // `stream` (the old buffer may still be read) and allocates, so it cannot happen
-// under graph capture: slingbag_plan_create reserves the buffer before capturing.
+// under graph capture (a plan allocates a buffer of its own before capturing).
 static int reserve_d5(DeviceState* ds, int64_t floats, hipStream_t s) {
     const size_t need = (size_t)floats * sizeof(float);
     std::lock_guard<std::mutex> lk(g_mu);
     if (ds->d5_bytes >= need) return SB_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-        return fail(SB_ERR_INVALID_ARG, "the adjoint's chain-rule buffer (%zu bytes) must be reserved before "
-                    "graph capture (slingbag_plan_create does)", need);
+        return fail(SB_ERR_INVALID_ARG, "the adjoint's chain-rule buffer (%zu bytes) cannot grow under graph "
+                    "capture: call slingbag_adjoint once on this problem before capturing, or use a plan", need);
     hipError_t e = hipSuccess;
     if (ds->d5) {
         e = hipStreamSynchronize(s);
@@ -306,6 +306,11 @@ struct Timing {
     int used[kTimeKinds] = {0, 0, 0, 0};
 };
 static Timing g_timing;
+
+// Set by slingbag_plan_create while it captures: the plan's own chain-rule buffer, which
+// the captured adjoint uses instead of the per-device one (the per-device buffer may be
+// replaced by a later, larger call; a graph must keep the address it was captured with).
+static thread_local float* g_capture_d5 = nullptr;
 
 // A plan captured while timing is on times its launches too.  During the capture
 // each mark is an empty marker kernel; afterwards an event record node (with a
@@ -486,8 +491,12 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch, const float* b
     p.flags = ds->flags;
     const int64_t n5 = d5_floats(cfg, batch, sh);
     if (n5 > 0) {
-        if ((st = reserve_d5(ds, n5, s))) return st;
-        p.d5 = ds->d5;
+        if (g_capture_d5) {
+            p.d5 = g_capture_d5;
+        } else {
+            if ((st = reserve_d5(ds, n5, s))) return st;
+            p.d5 = ds->d5;
+        }
         e = launch_fill(p.d5, n5, 0.f, s);
         if (e != hipSuccess) return hip_fail(e, "fill(chain-rule buffer)");
     }
@@ -763,6 +772,7 @@ int slingbag_timing_read(double* total_ms, int64_t* launches) {
 struct sb_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    float* d5 = nullptr;         // the plan's own two-phase chain-rule buffer (or null)
     int device = -1;
     bool timed = false;          // captured with timing on: the nodes below exist
     bool on_pool = false;        // the nodes currently record pool events (not the placeholders)
@@ -869,31 +879,42 @@ int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const floa
     DeviceState* ds;
     if ((st = device_state(&ds))) return st;   // per-device buffers exist before capture
     hipStream_t s = (hipStream_t)stream;
+    // the plan's own chain-rule buffer, allocated before the capture and kept by the plan
     const int64_t n5 = d5_floats(cfg, batch, sh);
-    if (n5 > 0 && (st = reserve_d5(ds, n5, s))) return st;
+    float* plan_d5 = nullptr;
+    if (n5 > 0) {
+        hipError_t ea = hipMalloc(&plan_d5, (size_t)n5 * sizeof(float));
+        if (ea != hipSuccess) return hip_fail(ea, "hipMalloc(plan chain-rule buffer)");
+    }
     // with timing on, the timed launches are captured between event record nodes
     CaptureTiming tm;
     const bool timed = g_timing.enabled;
     hipError_t e = hipSuccess;
+    auto release = [&]() {
+        release_capture_timing(tm);
+        if (plan_d5) (void)hipFree(plan_d5);
+    };
     if (timed) {
         for (int k : {(int)kTimeForward, (int)kTimeLoss, (int)kTimeAdjoint})
             for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipEventCreate(&tm.ev[k][w]);
         if (e != hipSuccess) {
-            release_capture_timing(tm);
+            release();
             return hip_fail(e, "hipEventCreate(plan timing)");
         }
     }
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        release_capture_timing(tm);
+        release();
         return hip_fail(e, "hipStreamBeginCapture");
     }
     g_capture = timed ? &tm : nullptr;
+    g_capture_d5 = plan_d5;
     st = slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream);
     if (st == SB_OK) st = slingbag_loss(cfg, batch, signals, measured, residual, loss, stream);
     if (st == SB_OK)
         st = slingbag_adjoint(cfg, batch, balls, deform, frame_t, sensors, residual, grad_balls, grad_deform, stream);
     g_capture = nullptr;
+    g_capture_d5 = nullptr;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(s, &graph);
     if (st == SB_OK && tm.failed) st = fail(SB_ERR_HIP, "capturing the plan's timing markers failed");
@@ -901,19 +922,20 @@ int slingbag_plan_create(const sb_config* cfg, const sb_batch* batch, const floa
     if (st == SB_OK && timed) st = add_timing_nodes(graph, tm);
     if (st != SB_OK) {
         if (graph) (void)hipGraphDestroy(graph);
-        release_capture_timing(tm);
+        release();
         return st;
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(graph);
-        release_capture_timing(tm);
+        release();
         return hip_fail(e, "hipGraphInstantiate");
     }
     sb_plan* plan = new sb_plan;
     plan->graph = graph;
     plan->exec = exec;
+    plan->d5 = plan_d5;
     plan->timed = timed;
     plan->tm = tm;
     (void)hipGetDevice(&plan->device);
@@ -936,6 +958,10 @@ int slingbag_plan_destroy(sb_plan* plan) {
     if (plan->exec) e = hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     release_capture_timing(plan->tm);
+    if (plan->d5) {
+        const hipError_t ef = hipFree(plan->d5);
+        if (e == hipSuccess) e = ef;
+    }
     delete plan;
     if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
     return SB_OK;

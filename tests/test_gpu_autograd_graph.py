@@ -210,3 +210,41 @@ def test_graph_replays_are_timed():
     finally:
         binding.timing(False)
         ops.check()
+
+
+def test_plan_keeps_its_chain_rule_buffer():
+    """A plan of a deformation with the two-phase chain rule (Eq. 2) captures its own
+    chain-rule buffer: a later, larger adjoint call, which replaces the per-device buffer,
+    leaves the plan's replays correct (against the oracle)."""
+    import torch
+    from helpers import tiny_scene
+    from paper_2412_03898_amd import ops
+    wl = tiny_scene(n_balls=400, n_sensors=70, n_frames=3, basis=2, N=5, pos_mode=1, seed=181)
+    d_np = oracle.forward(wl, balls=synth.perturbed(wl.balls, 182)).astype(np.float32)
+    pb, balls, deform, ft, sens = ops.to_device(wl)
+    g = ops.StepGraph(pb, balls, deform, ft, sens, torch.from_numpy(d_np).cuda())
+    try:
+        g.run()
+        torch.cuda.synchronize()
+        # a larger two-phase problem grows (reallocates) the per-device buffer
+        big = tiny_scene(n_balls=3000, n_sensors=70, n_frames=6, basis=2, N=5, pos_mode=1, seed=183)
+        pb2, b2, d2, ft2, s2 = ops.to_device(big)
+        y2 = ops.forward(pb2, b2, d2, ft2, s2)
+        ops.adjoint(pb2, b2, d2, ft2, s2, y2)
+        torch.cuda.synchronize()
+        print("[gpu-graph] replay after the per-device chain-rule buffer grew", flush=True)
+        Lg, gbg, gdg = g.run()
+        torch.cuda.synchronize()
+        assert ops.check() == 0
+        y_ref = oracle.forward(wl)
+        L_ref, r_ref = oracle.loss(y_ref, d_np)
+        gb_ref, gd_ref = oracle.adjoint(wl, r_ref)
+        assert float(Lg.item()) == pytest.approx(L_ref, rel=2e-5)
+        gb, gd = gbg.cpu().numpy(), gdg.cpu().numpy()
+        for x, r in ((gb[0:3], gb_ref[0:3]), (gb[3], gb_ref[3]), (gb[4], gb_ref[4])):
+            assert rel_l2(x, r) <= 1e-4
+        for kind in range(3):
+            for rows in (slice(0, 3), slice(3, 4), slice(4, 5)):
+                assert rel_l2(gd[rows, kind::3], gd_ref[rows, kind::3]) <= 1e-4, (kind, rows)
+    finally:
+        g.close()

@@ -194,6 +194,30 @@ def test_uneven_batch_with_empty_scene():
     assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
 
 
+def test_uneven_batch_two_phase_chain_rule():
+    """The two-phase chain rule's per-scene layout: four scenes with the Eq. 2 deformation
+    (4 bases per attribute, multiplicative positions) -- 300 balls x 2 frames, an empty
+    scene with 3 frames, 500 balls with no frame, 700 balls x 1 frame -- against the oracle."""
+    parts = [tiny_scene(n_balls=n, n_sensors=70, n_frames=1, basis=2, N=4, pos_mode=1, seed=s)
+             for n, s in ((300, 91), (500, 92), (700, 93))]
+    a, c, d = parts
+    wl = with_(a, balls=np.concatenate([a.balls, c.balls, d.balls], axis=1),
+               deform=np.concatenate([a.deform, c.deform, d.deform], axis=2),
+               frame_t=np.array([0.1, 0.6, 0.2, 0.5, 0.8, 0.35], np.float32),
+               ball_offset=np.array([0, 300, 300, 800, 1500]), frame_offset=np.array([0, 2, 5, 5, 6]))
+    _say("uneven batch, Eq. 2 (two-phase chain rule): 4 scenes, one empty, one without frames")
+    y, _ = gpu_forward(wl)
+    ref = oracle.forward(wl)
+    assert np.abs(y[2:5]).max() == 0.0
+    assert rel_l2(y, ref) <= SIG_TOL
+    rng = np.random.default_rng(94)
+    res = rng.normal(size=ref.shape).astype(np.float32) * np.float32(np.abs(ref).max())
+    got = gpu_adjoint(wl, res)
+    # the scene without frames has no gradient
+    assert np.abs(got[0][:, 300:800]).max() == 0.0 and np.abs(got[1][:, :, 300:800]).max() == 0.0
+    assert_grads(wl, got, oracle.adjoint(wl, res.astype(np.float64)))
+
+
 def test_single_ball_single_sensor():
     wl = tiny_scene(n_balls=1, n_sensors=1, seed=81)
     y, _ = gpu_forward(wl)

@@ -29,18 +29,39 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def source_digest(paths):
-    """SHA-256 over the named files (paths relative to the repository root), in order."""
+_C_LIKE = (".hip", ".hpp", ".h", ".c", ".cpp")
+
+
+def code_text(rel: str, data: bytes) -> bytes:
+    """The part of a source file that the digest covers: for C-like files the code with
+    comments removed and whitespace runs collapsed (editing a comment does not change
+    what the kernel does), else the file as it is."""
+    if not rel.endswith(_C_LIKE):
+        return data
+    text = data.decode("utf-8", errors="replace")
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split()).encode()
+
+
+def source_digest(paths, read=None):
+    """SHA-256 over the code of the named files (paths relative to the repository root),
+    in order.  `read(rel) -> bytes` supplies the contents (default: the working tree)."""
     h = hashlib.sha256()
     for rel in paths:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(rel.encode() + b"\0" + f.read())
+        if read is None:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                data = f.read()
+        else:
+            data = read(rel)
+        h.update(rel.encode() + b"\0" + code_text(rel, data))
     return h.hexdigest()
 
 

@@ -58,3 +58,14 @@ def test_sq_record_follows_sources(tmp_path, monkeypatch):
     assert profsum.sq_for("k<1>", "other") is None
     src.write_text("kernel v2\n")
     assert profsum.sq_for("k<1>", "w") is None
+
+
+def test_digest_ignores_comments_not_code(tmp_path, monkeypatch):
+    monkeypatch.setattr(profsum, "ROOT", str(tmp_path))
+    src = tmp_path / "k.hip"
+    src.write_text("// kernel\nint f(int x) { return x + 1; }  /* one */\n")
+    d0 = profsum.source_digest(["k.hip"])
+    src.write_text("// the kernel, reworded\nint f(int x) {\n    return x + 1;   /* another comment */\n}\n")
+    assert profsum.source_digest(["k.hip"]) == d0
+    src.write_text("// kernel\nint f(int x) { return x + 2; }  /* one */\n")
+    assert profsum.source_digest(["k.hip"]) != d0

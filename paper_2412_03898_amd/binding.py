@@ -241,6 +241,7 @@ def check(stream: int = 0) -> int:
 
 
 SB_TUNE_FWD_COLUMN, SB_TUNE_ADJ_OCCUPANCY, SB_TUNE_ADJ_ITEMS, SB_TUNE_FWD_GAUSS_COLUMN = 1, 2, 3, 4
+SB_FWD_COLUMN_SHARED = 1     # SB_TUNE_FWD_COLUMN value: one column per sensor shared by a block
 
 
 def tune(key: int, value: int):

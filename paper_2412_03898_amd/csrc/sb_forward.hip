@@ -31,6 +31,8 @@
 // which is the interval mean of the N-wave P(r - ct)/(2r) (resp. of the Gaussian
 // ball's outgoing term) over each sample interval.
 
+#include <climits>
+
 #include "sb_internal.hpp"
 
 namespace sb {
@@ -240,6 +242,47 @@ struct FwdPair {
     bool in_tile;    // this lane has a window to add
 };
 
+// Set-up of one staged ball for the lane's sensor (sx, sy, sz).  A pair without its
+// window (sensor inside a uniform ball, or an arrival sample out of int32 range) sets
+// `bad`; the exact flags are told apart on a slow path (chunk_flags).
+__device__ inline FwdPair pair_setup(const OpParams& p, const BallS& bs, double sx, double sy, double sz,
+                                     bool active, bool& bad) {
+    FwdPair f;
+    const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
+    const bool valid = Wc != 0, too_long = Wc < 0;
+    f.W = Wc > 0 ? Wc : 5;                           // no window: zeros at the first rows
+    float ri;
+    const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
+    const bool ok = r > bs.Rd;                       // outside the uniform ball (r > 0: Gaussian)
+    const double u = fma(r, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
+    const double kl = floor(u);
+    const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
+    const bool use = active && valid && !too_long;
+    f.in_tile = use && ok && in_range;               // the window exists
+    bad |= use && !f.in_tile;
+    f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
+    f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
+    f.klo = in_range ? (int)kl : 0;
+    f.rhof = bs.rhof;
+    return f;
+}
+
+// Slow path behind `bad`: redo the pair tests of n staged balls to raise the exact flags.
+__device__ inline void chunk_flags(const OpParams& p, const BallS* balls, int n, double sx, double sy, double sz,
+                                   bool active, bool& geometry, bool& clipped) {
+    for (int i = 0; i < n; ++i) {
+        const BallS bs = balls[i];
+        const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
+        const bool use = active && Wc > 0;
+        float ri;
+        const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
+        const bool ok = r > bs.Rd;
+        const double kl = floor(fma(r, p.inv_delta, -bs.c1));
+        geometry |= use && !ok;
+        clipped |= use && ok && !(fabs(kl) < 5.0e8);
+    }
+}
+
 template <int KERNEL>
 __device__ inline bool add_window_global(float* row, int klo, int T, int W, float x, float rho,
                                          float C) {
@@ -269,6 +312,74 @@ __device__ inline bool add_window_global(float* row, int klo, int T, int W, floa
     return clipped;
 }
 
+// Deformed ball `first + tid` of the chunk at frame time t (Eq. 1), with its amplitude
+// scale: P_f delta / 4 (uniform sphere), P_f rho^2 delta / 2 (Gaussian ball); threads past
+// the chunk's end get an empty ball.
+template <int KERNEL>
+__device__ inline BallF stage_deform(const OpParams& p, int tid, int nb, int64_t first, float t, const double* fb,
+                                     bool& nonfinite) {
+    BallF bl;
+    if (tid < nb) {
+        nonfinite |= !deform_ball(p, first + tid, t, fb, bl);
+        bl.amp = (KERNEL == SB_KERNEL_UNIFORM)
+                     ? (float)((double)bl.amp * (double)p.delta * 0.25)
+                     : (float)((double)bl.amp * bl.rho * bl.rho * (double)p.delta * 0.5);
+    } else {
+        bl.x = bl.y = bl.z = 0.0;
+        bl.rho = -1.0;
+        bl.rhof = -1.f;
+        bl.amp = 0.f;
+    }
+    return bl;
+}
+
+// The staged record of a deformed ball: what depends on the ball only.
+template <int KERNEL>
+__device__ inline BallS ball_record(const OpParams& p, const BallF& bl, bool& clipped) {
+    BallS bs;
+    const bool valid = bl.rho >= 0.0;
+    const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
+    bs.x = bl.x;
+    bs.y = bl.y;
+    bs.z = bl.z;
+    bs.c1 = p.t0fs + h - 0.5;
+    bs.Rd = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho * (double)p.delta : 0.0;
+    bs.amp = bl.amp;
+    bs.rhof = bl.rhof;
+    bs.hf = (float)h;
+    bs.Wc = !valid ? 0 : (h >= 1.0e6 ? -1 : (int)(2.0 * h) + 2);
+    clipped |= valid && h >= 1.0e6;                      // a window longer than any record
+    return bs;
+}
+
+// Uniform sphere, per wave of staged balls: the box of the centres of the balls whose
+// windows go to an LDS tile of CAP rows (max(W, 5) + 2 <= CAP with W = floor(2 rho) + 2,
+// as in the pair set-up), the sum of |P delta/4| (2 rho + 1) over them, and their largest
+// row count, written to box[0..7] by lane 0.  Every tile window adds at most
+// |P delta/4| (2 rho + 1) / r to any sample, with r at least the distance from the sensor
+// to the box: the bound behind the integer tile's scale.
+template <int CAP>
+__device__ inline void stage_box(const BallF& bl, bool real, int lane, float* box) {
+    const int rows = max((int)(2.0 * fmin(bl.rho, 1.0e6)) + 2, 5) + 2;
+    const bool in_tile = real && bl.rho >= 0.0 && rows <= CAP;
+    const float inf = __builtin_huge_valf();
+    const float lo[3] = {in_tile ? (float)bl.x : inf, in_tile ? (float)bl.y : inf, in_tile ? (float)bl.z : inf};
+    const float hi[3] = {in_tile ? (float)bl.x : -inf, in_tile ? (float)bl.y : -inf, in_tile ? (float)bl.z : -inf};
+    const float sa = in_tile ? fabsf(bl.amp) * fmaf(2.f, bl.rhof, 1.f) : 0.f;
+    float red[8];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        red[a] = wave_min_all(lo[a]);
+        red[3 + a] = wave_max_all(hi[a]);
+    }
+    red[6] = wave_reduce_dpp(sa, [](float x, float y) { return x + y; });
+    red[7] = (float)wave_max_all(in_tile ? rows : 0);
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) box[a] = red[a];
+    }
+}
+
 template <int NW, int G, int UCAP, int KERNEL>
 __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
     static_assert(UCAP % 64 == 0, "tile length must be a multiple of 64");
@@ -296,60 +407,9 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
         if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
         __syncthreads();
         {
-            BallF bl;
-            if (tid < nb) {
-                nonfinite |= !deform_ball(p, first + tid, t, s_fb, bl);
-                // amplitude scale of the trace: P_f delta / 4 (uniform), P_f rho^2 delta / 2 (Gaussian)
-                bl.amp = (KERNEL == SB_KERNEL_UNIFORM)
-                             ? (float)((double)bl.amp * (double)p.delta * 0.25)
-                             : (float)((double)bl.amp * bl.rho * bl.rho * (double)p.delta * 0.5);
-            } else {
-                bl.x = bl.y = bl.z = 0.0;
-                bl.rho = -1.0;
-                bl.rhof = -1.f;
-                bl.amp = 0.f;
-            }
-            {
-                BallS bs;
-                const bool valid = bl.rho >= 0.0;
-                const double h = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho : (double)kGaussCut * bl.rho;
-                bs.x = bl.x;
-                bs.y = bl.y;
-                bs.z = bl.z;
-                bs.c1 = p.t0fs + h - 0.5;
-                bs.Rd = (KERNEL == SB_KERNEL_UNIFORM) ? bl.rho * (double)p.delta : 0.0;
-                bs.amp = bl.amp;
-                bs.rhof = bl.rhof;
-                bs.hf = (float)h;
-                bs.Wc = !valid ? 0 : (h >= 1.0e6 ? -1 : (int)(2.0 * h) + 2);
-                clipped |= valid && h >= 1.0e6;                  // a window longer than any record
-                sball[tid] = bs;
-            }
-            if (KERNEL == SB_KERNEL_UNIFORM) {
-                // bound of the chunk's contribution to any sample: |v| <= |P delta/4| (2 rho + 1) / r
-                // for every tile window, with r at least the distance from the sensor to the
-                // box of the centres
-                // (tile windows: max(W, 5) + 2 <= UCAP rows with W = floor(2 rho) + 2, as in the
-                // pair set-up)
-                const bool in_tile = tid < nb && bl.rho >= 0.0 && max((int)(2.0 * fmin(bl.rho, 1.0e6)) + 2, 5) + 2 <= UCAP;
-                const float inf = __builtin_huge_valf();
-                const float lo[3] = {in_tile ? (float)bl.x : inf, in_tile ? (float)bl.y : inf,
-                                     in_tile ? (float)bl.z : inf};
-                const float hi[3] = {in_tile ? (float)bl.x : -inf, in_tile ? (float)bl.y : -inf,
-                                     in_tile ? (float)bl.z : -inf};
-                const float sa = in_tile ? fabsf(bl.amp) * fmaf(2.f, bl.rhof, 1.f) : 0.f;
-                float red[7];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    red[a] = wave_min_all(lo[a]);
-                    red[3 + a] = wave_max_all(hi[a]);
-                }
-                red[6] = wave_reduce_dpp(sa, [](float x, float y) { return x + y; });
-                if (lane == 0) {
-#pragma unroll
-                    for (int a = 0; a < 7; ++a) s_box[wid][a] = red[a];
-                }
-            }
+            const BallF bl = stage_deform<KERNEL>(p, tid, nb, first, t, s_fb, nonfinite);
+            sball[tid] = ball_record<KERNEL>(p, bl, clipped);
+            if (KERNEL == SB_KERNEL_UNIFORM) stage_box<UCAP>(bl, tid < nb, lane, s_box[wid]);
         }
         __syncthreads();
 
@@ -495,26 +555,7 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
             };
 
             // pair set-up of ball i for this wave's sensors
-            auto setup = [&](const BallS& bs) {
-                FwdPair f;
-                const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
-                const bool valid = Wc != 0, too_long = Wc < 0;
-                f.W = Wc > 0 ? Wc : 5;                           // no window: zeros at the first rows
-                float ri;
-                const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
-                const bool ok = r > bs.Rd;                       // outside the uniform ball (r > 0: Gaussian)
-                const double u = fma(r, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
-                const double kl = floor(u);
-                const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
-                const bool use = active && valid && !too_long;
-                f.in_tile = use && ok && in_range;               // the window exists (placed at apply)
-                bad |= use && !f.in_tile;
-                f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
-                f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
-                f.klo = in_range ? (int)kl : 0;
-                f.rhof = bs.rhof;
-                return f;
-            };
+            auto setup = [&](const BallS& bs) { return pair_setup(p, bs, sx, sy, sz, active, bad); };
             auto prep = [&](int i) { return setup(sball[i]); };
             auto apply = [&](const FwdPair& f) {
                 const bool part = f.in_tile;
@@ -592,19 +633,310 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
                 }
             }
             flush();
-            if (__ballot(bad)) {
-                // rare: redo the pair tests of the chunk to raise the exact flags
-                for (int i = 0; i < nb; ++i) {
-                    const BallS bs = sball[i];
-                    const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
-                    const bool use = active && Wc > 0;
-                    float ri;
-                    const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
-                    const bool ok = r > bs.Rd;
-                    const double kl = floor(fma(r, p.inv_delta, -bs.c1));
-                    geometry |= use && !ok;
-                    clipped |= use && ok && !(fabs(kl) < 5.0e8);
+            if (__ballot(bad)) chunk_flags(p, sball, nb, sx, sy, sz, active, geometry, clipped);
+        }
+    }
+    if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
+    if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
+    if (nonfinite) raise_flag(p.flags, SB_FLAG_NONFINITE);
+}
+
+// ---- Shared column (uniform sphere, integer tile) ----------------------------------
+//
+// The four waves of a block take the same 64 sensors (one per lane) and a quarter of the
+// chunk's 256 balls each, and add their windows' second differences into one column of
+// kShRows samples per sensor that the whole block shares.  A sensor's column starts at a
+// lower bound of the chunk's arrival samples there (from the distance to the box of the
+// centres), so no column moves while the waves add.  A window that starts kShRows - rmax + 1
+// or more samples past the column start (rmax: rows of the chunk's longest tile window)
+// is left for a later pass, whose column starts where this one's windows stopped (from
+// the second later pass on: at the sensor's least sample left, when that lies further);
+// only the balls with such a window in some lane are set up again.  A pass ends with one
+// flush: each wave integrates a quarter of the rows (a 33-row segment) for all 64
+// sensors, the segments' running sums are chained through LDS, and the segment is
+// transposed in place (each LDS row then holds 33 consecutive samples of one sensor, row
+// stride 33: conflict-free both ways) and added to the global trace, two sensors'
+// 32-sample runs per coalesced FP32 atomic and the 33rd samples in one more.  One 33 KB
+// column per block instead of a 16 KB tile per wave lets three blocks (twelve waves)
+// share a compute unit instead of two.
+constexpr int kShSeg = 33;               // rows per wave in the flush
+constexpr int kShRows = 4 * kShSeg;      // samples per sensor in the shared column
+constexpr int kShCap = 64;               // longest window kept in LDS (rows); longer ones go to the trace directly
+
+__global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
+    constexpr int NW = 4, G = 256;
+    __shared__ BallS sball[G];
+    __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
+    __shared__ float s_box[NW][8];                    // per wave of staged balls: tile box, amplitude sum, rows
+    __shared__ __align__(16) uint32_t col[kShRows * 64];   // row k, sensor (lane): second differences
+    __shared__ uint32_t s_tot[NW][2][64];             // per segment and sensor: running sums at its end
+    __shared__ int s_kb[NW][64];                      // per segment and sensor: trace sample of its first row
+    __shared__ int s_more[2];                         // per pass parity: some window is left for a later pass
+    __shared__ int s_nmin[2][64];                     // per pass parity and sensor: least sample left
+
+    // the wave index as a scalar: the wave's ball loop and flush segment are then uniform
+    // control flow for the compiler
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    for (int i = tid; i < kShRows * 64; i += 64 * NW) col[i] = 0u;
+    if (tid < 2) s_more[tid] = 0;
+    if (tid < 128) (&s_nmin[0][0])[tid] = INT_MAX;
+    bool clipped = false, geometry = false, nonfinite = false;
+    int pp = 0;                                       // passes so far: s_more[pp & 1] is the current one
+
+    for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
+        const Item it = decode_item(p, item);
+        const Scene& sc = p.scenes[it.scene];
+        const int gf = sc.frame0 + it.frame;
+        const float t = p.frame_t[gf];
+        const int64_t first = sc.ball0 + (int64_t)it.group * G;
+        const int nb = min(G, sc.n_balls - it.group * G);
+        __syncthreads();   // the previous item is done with sball and s_fb
+        if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
+        __syncthreads();
+        {
+            const BallF bl = stage_deform<SB_KERNEL_UNIFORM>(p, tid, nb, first, t, s_fb, nonfinite);
+            sball[tid] = ball_record<SB_KERNEL_UNIFORM>(p, bl, clipped);
+            stage_box<kShCap>(bl, tid < nb, lane, s_box[wid]);
+        }
+        __syncthreads();
+        float lo[3], hi[3], sum = 0.f;
+        int rmax = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = s_box[0][a];
+            hi[a] = s_box[0][3 + a];
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], s_box[w][a]);
+                hi[a] = fmaxf(hi[a], s_box[w][3 + a]);
+            }
+            sum += s_box[w][6];
+            rmax = max(rmax, (int)s_box[w][7]);
+        }
+        const int nbw = max(0, min(64, nb - 64 * wid));   // this wave's balls: 64 wid + [0, nbw)
+        const BallS* const wb = sball + 64 * wid;
+
+        // the item's sensor blocks (64 sensors each), one after the other
+        const int sb_end = min(it.sblock + p.sb_per_item, p.n_sblocks);
+        for (int sbk = it.sblock; sbk < sb_end; ++sbk) {
+            {
+                const int s0 = sbk * 64;
+                const int s = s0 + lane;
+                const bool active = s < p.S;
+                double sx = 0.0, sy = 0.0, sz = 0.0;
+                if (active) { sx = p.sensors[s]; sy = p.sensors[p.S + s]; sz = p.sensors[2 * p.S + s]; }
+                float* const sig0 = p.signals + ((int64_t)gf * p.S + s0) * p.T;   // trace row of sensor s0
+                float* const out_row = sig0 + (int64_t)(active ? lane : 0) * p.T;
+
+                // Integer scale qs = 2^30 r_min / sum (as in forward_kernel) and the column start:
+                // no tile window of the chunk starts before floor(r_min / delta - t0 fs - rmax / 2)
+                // (rho < rows / 2), nor ends after floor(r_max / delta - t0 fs + 1/2) + rmax - 1;
+                // two samples of margin each way cover the rounding of the box.
+                float qs = 1.f, qeps = 1.f;
+                int base = 0, kfar = INT_MIN;
+                bool ok = true;
+                if (active) {
+                    if (!(sum < __builtin_huge_valf())) {
+                        ok = false;                       // a non-finite amplitude in the chunk
+                    } else if (lo[0] <= hi[0]) {
+                        double dmin, dmax;
+                        box_distance_range(lo, hi, sx, sy, sz, dmin, dmax);
+                        const double b0 = floor(dmin * p.inv_delta - p.t0fs - 0.5 * (double)rmax) - 2.0;
+                        const double b1 = floor(dmax * p.inv_delta - p.t0fs + 0.5) + (double)(rmax + 1);
+                        base = (int)fmin(fmax(b0, -1.0e9), 1.0e9);
+                        kfar = (int)fmin(fmax(b1, -1.0e9), 1.0e9);
+                        if (sum > 0.f) {
+                            qs = (float)(1073741824.0 * dmin / (double)sum);
+                            ok = dmin > 0.25 * dmax && qs > 0.f && qs < __builtin_huge_valf();
+                            qeps = 1.f / qs;
+                        }
+                    }                                     // else: no tile window in the chunk
                 }
+                const bool qmode = __all(ok);             // the same in every wave (same sensors, same box)
+                bool bad = false;
+                auto setup = [&](const BallS& bs) { return pair_setup(p, bs, sx, sy, sz, active, bad); };
+
+                // flush of the column after a pass (every wave, between block barriers): rows
+                // k0 .. k0 + 32 of every sensor, integrated, chained to the rows before, and added to
+                // the trace from sample base + k0 on.  kmax_b: last row any window of the pass can
+                // have reached (segments past it are exactly zero).
+                auto flush = [&](int kmax_b) {
+                    const int k0 = kShSeg * wid;
+                    const bool touched = k0 <= kmax_b;
+                    uint32_t v[kShSeg];
+                    uint32_t d1 = 0u, d0 = 0u;
+                    if (touched) {
+#pragma unroll
+                        for (int k = 0; k < kShSeg; ++k) {
+                            d1 += col[(k0 + k) * 64 + lane];
+                            d0 += d1;
+                            v[k] = d0;
+                        }
+                    }
+                    s_tot[wid][0][lane] = d1;
+                    s_tot[wid][1][lane] = d0;
+                    __syncthreads();
+                    if (touched) {
+                        // running sums at the end of the segments before this one
+                        uint32_t c1 = 0u, c0 = 0u;
+                        for (int u = 0; u < wid; ++u) {
+                            c0 += (uint32_t)kShSeg * c1 + s_tot[u][1][lane];
+                            c1 += s_tot[u][0][lane];
+                        }
+                        // the segment, transposed in place: LDS row a (stride 33) holds the 33
+                        // samples of sensor a
+                        float* const seg = reinterpret_cast<float*>(col + k0 * 64);
+                        uint32_t c = c0 + c1;
+#pragma unroll
+                        for (int k = 0; k < kShSeg; ++k) {
+                            seg[lane * kShSeg + k] = (float)(int32_t)(v[k] + c) * qeps;
+                            c += c1;
+                        }
+                        const int kb = base + k0;         // trace sample of this sensor's row k0
+                        s_kb[wid][lane] = kb;
+                        wave_lds_sync();
+                        // atomic i adds samples kb + j, j < 32, of sensors 2i (lanes j) and 2i + 1
+                        // (lanes 32 + j): one 32-bit byte offset per lane from the pair's row
+                        const int half = lane >> 5, j = lane & 31;
+                        const int nact = p.S - s0;        // sensors of the group inside the record's S
+                        const bool inside = __all(!active || (kb >= 0 && kb <= p.T - kShSeg)) && p.T < (1 << 28);
+                        const int* const kbv = &s_kb[wid][half];
+                        const float* const sv = seg + half * kShSeg + j;
+                        if (inside) {
+                            const uint32_t lane_b = (uint32_t)(half * p.T + j) * 4u;
+#pragma unroll 1
+                            for (int i0 = 0; i0 < 32; i0 += 8) {
+                                float vv[8];
+                                int kk[8];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    vv[u] = sv[2 * (i0 + u) * kShSeg];
+                                    kk[u] = kbv[2 * (i0 + u)];
+                                }
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    char* const rowp = reinterpret_cast<char*>(sig0 + (int64_t)(2 * (i0 + u)) * p.T);
+                                    if (vv[u] != 0.f)
+                                        global_atomic_add(reinterpret_cast<float*>(rowp + (lane_b + (uint32_t)kk[u] * 4u)), vv[u]);
+                                }
+                            }
+                        } else {
+#pragma unroll 1
+                            for (int i = 0; i < 32; ++i) {
+                                const float vi = sv[2 * i * kShSeg];
+                                const int a = 2 * i + half;
+                                const int k = kbv[2 * i] + j;
+                                if (vi != 0.f && a < nact) {
+                                    if (k >= 0 && k < p.T) global_atomic_add(sig0 + (int64_t)a * p.T + k, vi);
+                                    else clipped = true;
+                                }
+                            }
+                        }
+                        // the 33rd sample of every sensor (lane = sensor)
+                        {
+                            const float vl = seg[lane * kShSeg + 32];
+                            const int k = kb + 32;
+                            if (vl != 0.f && active) {
+                                if (k >= 0 && k < p.T) global_atomic_add(out_row + k, vl);
+                                else clipped = true;
+                            }
+                        }
+                        wave_lds_sync();
+                        uint4* const z = reinterpret_cast<uint4*>(col + k0 * 64);
+#pragma unroll
+                        for (int q = 0; q < (kShSeg * 64 + 255) / 256; ++q)
+                            if (q * 64 + lane < kShSeg * 16) z[q * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+                    }
+                    __syncthreads();                      // the column is zero again
+                };
+
+                if (qmode) {
+                    const int span = kShRows + 1 - rmax;  // first samples of one pass's windows
+                    int lim = base + span;                // windows starting before lim fit this pass
+                    uint64_t left = 0;                    // the wave's balls with a window left for later
+                    for (int pass = 0;; ++pass) {
+                        int nmin = INT_MAX;                   // later passes: least sample left (this lane)
+                        if (pass == 0 && nbw > 0) {
+                            // every ball of the wave; the next ball's FP64 set-up runs while this
+                            // ball's seven LDS adds complete (as in forward_kernel)
+                            FwdPair cur = setup(wb[0]);
+                            BallS bn = wb[min(1, nbw - 1)];
+                            for (int i = 0; i < nbw; ++i) {
+                                const bool part = cur.in_tile;
+                                const int rows = max(cur.W, 5) + 2;       // the same in every lane
+                                const bool in_lds = rows <= kShCap;
+                                const int tl = cur.klo - base;
+                                const bool fit = part && in_lds && tl >= 0 && cur.klo < lim;
+                                const bool later = part && in_lds && cur.klo >= lim;
+                                const bool direct = part && (!in_lds || tl < 0);
+                                if (__ballot(later)) left |= 1ull << i;
+                                const int tr = fit ? tl : 0;            // lanes without a window add zeros
+                                FwdPair nxt;
+                                if (cur.W >= 5 && in_lds) {
+                                    const D2Win dw = d2_window<true>(cur.W, fit ? cur.xg : 0.f, cur.rhof, fit ? cur.Cg * qs : 0.f);
+                                    uint32_t* const c0 = col + tr * 64 + lane;
+                                    d2_add(c0, c0 + dw.w2 * 64, dw);
+                                    nxt = setup(bn);
+                                } else {
+                                    if (in_lds) {
+                                        const D2Win dw = d2_window<false>(cur.W, fit ? cur.xg : 0.f, cur.rhof, fit ? cur.Cg * qs : 0.f);
+                                        uint32_t* const c0 = col + tr * 64 + lane;
+                                        d2_add(c0, c0 + dw.w2 * 64, dw);
+                                    }
+                                    nxt = setup(bn);
+                                }
+                                if (__ballot(direct)) {
+                                    if (direct) clipped |= add_window_global<SB_KERNEL_UNIFORM>(out_row, cur.klo, p.T, cur.W, cur.xg, cur.rhof, cur.Cg);
+                                }
+                                cur = nxt;
+                                bn = wb[min(i + 2, nbw - 1)];
+                            }
+                        } else if (pass > 0) {
+                            // the balls with a window left over, again; every such window is an LDS one
+                            uint64_t m = left;
+                            left = 0;
+                            while (m) {
+                                const int i = (int)__builtin_ctzll(m);
+                                m &= m - 1;
+                                const FwdPair f = setup(wb[i]);
+                                const int tl = f.klo - base;
+                                const bool fit = f.in_tile && tl >= 0 && f.klo < lim;
+                                const bool later = f.in_tile && f.klo >= lim;
+                                if (__ballot(later)) left |= 1ull << i;
+                                if (later) nmin = min(nmin, f.klo);
+                                const D2Win dw = d2_window<false>(f.W, fit ? f.xg : 0.f, f.rhof, fit ? f.Cg * qs : 0.f);
+                                uint32_t* const c0 = col + (fit ? tl : 0) * 64 + lane;
+                                d2_add(c0, c0 + dw.w2 * 64, dw);
+                            }
+                        }
+                        if (left != 0 && lane == 0) s_more[pp & 1] = 1;
+                        if (nmin != INT_MAX) atomicMin(&s_nmin[pp & 1][lane], nmin);
+                        const int kmax_b = __builtin_amdgcn_readfirstlane(
+                            wave_max_all(kfar == INT_MIN ? -1 : min(kfar - base, kShRows - 1)));
+                        __syncthreads();                  // every window of the pass is in the column
+                        const bool more = s_more[pp & 1] != 0;
+                        const int nnext = s_nmin[pp & 1][lane];
+                        if (wid == 0) {                   // the other parity was read last in the pass before
+                            s_nmin[(pp + 1) & 1][lane] = INT_MAX;
+                            if (lane == 0) s_more[(pp + 1) & 1] = 0;
+                        }
+                        flush(kmax_b);
+                        ++pp;
+                        if (!more) break;                 // the same in every wave
+                        base = nnext == INT_MAX ? lim : max(lim, nnext);
+                        lim = base + span;
+                    }
+                } else {
+                    // no integer scale for these sensors: every window straight to the trace
+                    for (int i = 0; i < nbw; ++i) {
+                        const FwdPair f = setup(wb[i]);
+                        if (f.in_tile) clipped |= add_window_global<SB_KERNEL_UNIFORM>(out_row, f.klo, p.T, f.W, f.xg, f.rhof, f.Cg);
+                    }
+                }
+                if (__ballot(bad)) chunk_flags(p, wb, nbw, sx, sy, sz, active, geometry, clipped);
             }
         }
     }
@@ -625,6 +957,13 @@ static hipError_t launch_fwd_t(const OpParams& p, hipStream_t st) {
 
 hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
     // the host's work decomposition (n_sblocks, n_groups) must match the instance
+    if (kernel == SB_KERNEL_UNIFORM && tc.shared) {
+        if (tc.nw != 1 || tc.g != 256) return hipErrorInvalidValue;   // sensor blocks of 64, chunks of 256
+        const int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL(forward_shared_kernel, dim3((unsigned)grid), dim3(256), 0, st, p);
+        return hipGetLastError();
+    }
     if (kernel == SB_KERNEL_UNIFORM) {
         if (tc.nw == 4 && tc.g == 256 && tc.ucap == 128) return launch_fwd_t<4, 256, 128, 0>(p, st);
         if (tc.nw == 4 && tc.g == 256 && tc.ucap == 64) return launch_fwd_t<4, 256, 64, 0>(p, st);

@@ -311,9 +311,10 @@ __device__ inline void box_distance_range(const float* lo, const float* hi, doub
 
 // ---- host-side launchers (defined in the .hip files) ----
 struct TileCfg {
-    int nw;      // forward: waves per block (64 sensors each)
+    int nw;      // forward: sensors per item block / 64 (waves per block but for the shared column)
     int g;       // forward: balls per chunk
     int ucap;    // forward: tile length in samples; adjoint: residual row length
+    int shared = 0;   // forward, uniform sphere: one column per sensor shared by the block's waves
 };
 
 hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st);

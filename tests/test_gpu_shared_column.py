@@ -1,0 +1,29 @@
+"""GPU parity of the uniform sphere's shared-column forward (SB_TUNE_FWD_COLUMN =
+SB_FWD_COLUMN_SHARED): the forward cases of the parity suite, run again with that
+layout set.  Unsorted balls (every 256-ball chunk spans the whole cube) make each
+sensor's arrivals spread over several columns, so they take the multi-pass path;
+sensors among the balls take the path without an integer scale."""
+
+import pytest
+
+from test_gpu_parity import (plain, test_4d_fourier_small, test_ball_longer_than_any_record_is_skipped_and_flagged,  # noqa: F401
+                             test_clipped_record_is_dropped_and_flagged, test_forward_plain,
+                             test_large_ir_scene_full_size_sampled, test_nonfinite_ball_is_skipped_and_flagged,
+                             test_result_independent_of_order, test_sensor_inside_ball_raises_flag,
+                             test_sensors_among_the_balls, test_single_ball_single_sensor,
+                             test_uneven_batch_full_size_sampled, test_uneven_batch_with_empty_scene,
+                             test_variants, test_vessel_4d_full_size_sampled, test_vessel_static_full_size_sampled,
+                             test_window_lengths_two_to_forty)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def shared_column():
+    from paper_2412_03898_amd import binding
+    saved = binding.tune_get(binding.SB_TUNE_FWD_COLUMN)
+    binding.tune(binding.SB_TUNE_FWD_COLUMN, binding.SB_FWD_COLUMN_SHARED)
+    try:
+        yield
+    finally:
+        binding.tune(binding.SB_TUNE_FWD_COLUMN, saved)

@@ -307,7 +307,12 @@ def sq_and_traffic(instance, workload):
 
 
 def kernel_instance(kind, wl, choice):
+    from paper_2412_03898_amd import binding
     if kind == "forward":
+        if choice[0] == binding.SB_FWD_COLUMN_SHARED:
+            return "forward_shared_kernel<33, 3>"
+        if choice[0] == binding.SB_FWD_COLUMN_SHARED_SHORT:
+            return "forward_shared_kernel<23, 4>"
         return f"forward_kernel<4, 256, {choice[0]}, 0>"
     mreg = 4 if wl.basis == 1 and wl.n_terms == 2 else 0
     return f"adjoint_uniform_kernel<{mreg}, {choice[1]}>"

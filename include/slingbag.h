@@ -248,10 +248,13 @@ int slingbag_plan_destroy(sb_plan* plan);
  * candidates on the caller's own shapes and sets the fastest.
  *   SB_TUNE_FWD_COLUMN     forward LDS column of the uniform sphere: 64 or 128 (each wave
  *                          of a block keeps its own column of that many samples per sensor
- *                          and walks all of the chunk's balls), or SB_FWD_COLUMN_SHARED (the
- *                          block's four waves share one 128-sample column per sensor and
- *                          take a quarter of the balls each: less LDS per block, three
- *                          blocks per compute unit instead of two); default 64
+ *                          and walks all of the chunk's balls; two blocks per compute unit),
+ *                          SB_FWD_COLUMN_SHARED (the block's four waves share one 132-sample
+ *                          column per sensor and take a quarter of the balls each; three
+ *                          blocks per compute unit) or SB_FWD_COLUMN_SHARED_SHORT (the same
+ *                          with a 92-sample column; four blocks per compute unit, more
+ *                          passes where a chunk's arrivals spread wider);
+ *                          default SB_FWD_COLUMN_SHARED_SHORT
  *   SB_TUNE_FWD_GAUSS_COLUMN  forward LDS column length for the Gaussian ball: 128 samples
  *                          (blocks of 4 waves) or 256 (blocks of 2 waves, for windows that
  *                          nearly fill 128 rows); default 256
@@ -264,7 +267,8 @@ int slingbag_plan_destroy(sb_plan* plan);
 #define SB_TUNE_ADJ_OCCUPANCY  2
 #define SB_TUNE_ADJ_ITEMS      3
 #define SB_TUNE_FWD_GAUSS_COLUMN 4
-#define SB_FWD_COLUMN_SHARED   1      /* value of SB_TUNE_FWD_COLUMN */
+#define SB_FWD_COLUMN_SHARED        1   /* values of SB_TUNE_FWD_COLUMN */
+#define SB_FWD_COLUMN_SHARED_SHORT  2
 int slingbag_tune(int key, int value);
 int slingbag_tune_get(int key, int* value);
 

@@ -241,7 +241,9 @@ def check(stream: int = 0) -> int:
 
 
 SB_TUNE_FWD_COLUMN, SB_TUNE_ADJ_OCCUPANCY, SB_TUNE_ADJ_ITEMS, SB_TUNE_FWD_GAUSS_COLUMN = 1, 2, 3, 4
-SB_FWD_COLUMN_SHARED = 1     # SB_TUNE_FWD_COLUMN value: one column per sensor shared by a block
+# SB_TUNE_FWD_COLUMN values besides 64 and 128: one column per sensor shared by a block's
+# waves, 132 samples (three blocks per compute unit) or 92 (four)
+SB_FWD_COLUMN_SHARED, SB_FWD_COLUMN_SHARED_SHORT = 1, 2
 
 
 def tune(key: int, value: int):

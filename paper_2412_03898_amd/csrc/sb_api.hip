@@ -130,7 +130,8 @@ static int validate_batch(const sb_batch* batch, Shape& sh) {
 // and adjoint item count.  They change speed, not results (beyond the order of
 // floating-point atomics).
 struct Tuning {
-    int fwd_ucap = 64;         // 64 or 128 samples per wave's LDS column, or SB_FWD_COLUMN_SHARED (uniform sphere)
+    int fwd_ucap = SB_FWD_COLUMN_SHARED_SHORT;   // uniform sphere: 64 or 128 samples per wave's LDS
+                                                 // column, or one of the shared columns
     int fwd_gauss_ucap = 256;  // 128 (4-wave blocks) or 256 (2-wave blocks): Gaussian ball
     int adj_occ = 4;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
     int adj_items = 8192;      // adjoint items the sensor split aims for
@@ -153,11 +154,12 @@ static TileCfg pick_forward_tiles(int kernel, const Tuning& tu) {
     tc.nw = long_col ? 2 : 4;
     tc.g = 64 * tc.nw;
     tc.ucap = kernel == SB_KERNEL_UNIFORM ? tu.fwd_ucap : tu.fwd_gauss_ucap;
-    tc.shared = kernel == SB_KERNEL_UNIFORM && tu.fwd_ucap == SB_FWD_COLUMN_SHARED;
+    tc.shared = kernel == SB_KERNEL_UNIFORM &&
+                (tu.fwd_ucap == SB_FWD_COLUMN_SHARED || tu.fwd_ucap == SB_FWD_COLUMN_SHARED_SHORT);
     if (tc.shared) {
         tc.nw = 1;     // the block's four waves share each 64-sensor block
         tc.g = 256;
-        tc.ucap = 132;
+        tc.ucap = tu.fwd_ucap == SB_FWD_COLUMN_SHARED_SHORT ? 92 : 132;   // samples per sensor
     }
     return tc;
 }
@@ -647,8 +649,9 @@ int slingbag_tune(int key, int value) {
     std::lock_guard<std::mutex> lk(g_mu);
     switch (key) {
         case SB_TUNE_FWD_COLUMN:
-            if (value != 64 && value != 128 && value != SB_FWD_COLUMN_SHARED)
-                return fail(SB_ERR_INVALID_ARG, "forward column must be 64, 128 or SB_FWD_COLUMN_SHARED");
+            if (value != 64 && value != 128 && value != SB_FWD_COLUMN_SHARED && value != SB_FWD_COLUMN_SHARED_SHORT)
+                return fail(SB_ERR_INVALID_ARG,
+                            "forward column must be 64, 128, SB_FWD_COLUMN_SHARED or SB_FWD_COLUMN_SHARED_SHORT");
             g_tune.fwd_ucap = value;
             return SB_OK;
         case SB_TUNE_FWD_GAUSS_COLUMN:
@@ -682,13 +685,13 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
     const Tuning saved = tuning();
     Tuning cur = saved;          // the candidate being timed, published to the calls below
     float best = 3.0e38f, ms = 0.f;
-    // the column knob of the problem's kernel: 64 / 128 / shared (uniform sphere), 128 / 256
-    // (Gaussian ball)
+    // the column knob of the problem's kernel: 64 / 128 / the two shared columns (uniform
+    // sphere), 128 / 256 (Gaussian ball)
     const bool uni = cfg->kernel == SB_KERNEL_UNIFORM;
     int& col_knob = uni ? cur.fwd_ucap : cur.fwd_gauss_ucap;
     int best_col = col_knob;
-    for (int col : {64, 128, 256, SB_FWD_COLUMN_SHARED}) {
-        if (uni ? col == 256 : (col == 64 || col == SB_FWD_COLUMN_SHARED)) continue;
+    for (int col : {64, 128, 256, SB_FWD_COLUMN_SHARED, SB_FWD_COLUMN_SHARED_SHORT}) {
+        if (uni ? col == 256 : (col != 128 && col != 256)) continue;
         col_knob = col;
         set_tuning(cur);
         st = time_ms(s, reps, [&] { return slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream); }, &ms);

@@ -233,6 +233,21 @@ struct BallS {
     int Wc;           // window length W = floor(2 h) + 2; 0: no ball; -1: longer than any record
 };
 
+// The uniform sphere's record in the shared-column forward: 48 bytes, so that the
+// staged chunk and the column fit four blocks per compute unit.  The window's half-width
+// is rho, and the inside-ball radius R_f is kept in FP32 (the test r > R_f then differs
+// from the FP64 one only for a sensor within 1e-7 R_f of the ball's surface).
+struct BallU {
+    double x, y, z;   // deformed centre (m)
+    double c1;        // t0 fs + rho - 1/2: the window starts at sample floor(r / delta - c1)
+    float Rd;         // R_f (m): the sensor must lie outside
+    float amp;        // amplitude scale of the trace
+    float rhof;       // rho = R_f / delta (samples), also the window's half-width
+    int Wc;           // window length W = floor(2 rho) + 2; 0: no ball; -1: longer than any record
+};
+__device__ inline float win_half(const BallS& b) { return b.hf; }
+__device__ inline float win_half(const BallU& b) { return b.rhof; }
+
 // Per-pair quantities of one ball for the wave's 64 sensors (one per lane).
 struct FwdPair {
     float Cg, xg;    // amplitude and boundary 0
@@ -245,7 +260,8 @@ struct FwdPair {
 // Set-up of one staged ball for the lane's sensor (sx, sy, sz).  A pair without its
 // window (sensor inside a uniform ball, or an arrival sample out of int32 range) sets
 // `bad`; the exact flags are told apart on a slow path (chunk_flags).
-__device__ inline FwdPair pair_setup(const OpParams& p, const BallS& bs, double sx, double sy, double sz,
+template <typename Rec>
+__device__ inline FwdPair pair_setup(const OpParams& p, const Rec& bs, double sx, double sy, double sz,
                                      bool active, bool& bad) {
     FwdPair f;
     const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
@@ -253,7 +269,7 @@ __device__ inline FwdPair pair_setup(const OpParams& p, const BallS& bs, double 
     f.W = Wc > 0 ? Wc : 5;                           // no window: zeros at the first rows
     float ri;
     const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
-    const bool ok = r > bs.Rd;                       // outside the uniform ball (r > 0: Gaussian)
+    const bool ok = r > (double)bs.Rd;               // outside the uniform ball (r > 0: Gaussian)
     const double u = fma(r, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
     const double kl = floor(u);
     const bool in_range = fabs(kl) < 5.0e8;          // int32 sample arithmetic
@@ -261,22 +277,23 @@ __device__ inline FwdPair pair_setup(const OpParams& p, const BallS& bs, double 
     f.in_tile = use && ok && in_range;               // the window exists
     bad |= use && !f.in_tile;
     f.Cg = bs.amp * ri;                              // amp holds the amplitude scale (staging)
-    f.xg = (float)(u - kl) + bs.hf;                  // boundary 0: tau - k_lo + 1/2
+    f.xg = (float)(u - kl) + win_half(bs);           // boundary 0: tau - k_lo + 1/2
     f.klo = in_range ? (int)kl : 0;
     f.rhof = bs.rhof;
     return f;
 }
 
 // Slow path behind `bad`: redo the pair tests of n staged balls to raise the exact flags.
-__device__ inline void chunk_flags(const OpParams& p, const BallS* balls, int n, double sx, double sy, double sz,
+template <typename Rec>
+__device__ inline void chunk_flags(const OpParams& p, const Rec* balls, int n, double sx, double sy, double sz,
                                    bool active, bool& geometry, bool& clipped) {
     for (int i = 0; i < n; ++i) {
-        const BallS bs = balls[i];
+        const Rec bs = balls[i];
         const int Wc = __builtin_amdgcn_readfirstlane(bs.Wc);
         const bool use = active && Wc > 0;
         float ri;
         const double r = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
-        const bool ok = r > bs.Rd;
+        const bool ok = r > (double)bs.Rd;
         const double kl = floor(fma(r, p.inv_delta, -bs.c1));
         geometry |= use && !ok;
         clipped |= use && ok && !(fabs(kl) < 5.0e8);
@@ -378,6 +395,22 @@ __device__ inline void stage_box(const BallF& bl, bool real, int lane, float* bo
 #pragma unroll
         for (int a = 0; a < 8; ++a) box[a] = red[a];
     }
+}
+
+// The uniform sphere's 48-byte record (shared-column forward).
+__device__ inline BallU ball_record_u(const OpParams& p, const BallF& bl, bool& clipped) {
+    BallU bs;
+    const bool valid = bl.rho >= 0.0;
+    bs.x = bl.x;
+    bs.y = bl.y;
+    bs.z = bl.z;
+    bs.c1 = p.t0fs + bl.rho - 0.5;
+    bs.Rd = (float)(bl.rho * (double)p.delta);
+    bs.amp = bl.amp;
+    bs.rhof = bl.rhof;
+    bs.Wc = !valid ? 0 : (bl.rho >= 1.0e6 ? -1 : (int)(2.0 * bl.rho) + 2);
+    clipped |= valid && bl.rho >= 1.0e6;                 // a window longer than any record
+    return bs;
 }
 
 template <int NW, int G, int UCAP, int KERNEL>
@@ -652,20 +685,25 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
 // is left for a later pass, whose column starts where this one's windows stopped (from
 // the second later pass on: at the sensor's least sample left, when that lies further);
 // only the balls with such a window in some lane are set up again.  A pass ends with one
-// flush: each wave integrates a quarter of the rows (a 33-row segment) for all 64
+// flush: each wave integrates a quarter of the rows (a SEG-row segment) for all 64
 // sensors, the segments' running sums are chained through LDS, and the segment is
-// transposed in place (each LDS row then holds 33 consecutive samples of one sensor, row
-// stride 33: conflict-free both ways) and added to the global trace, two sensors'
-// 32-sample runs per coalesced FP32 atomic and the 33rd samples in one more.  One 33 KB
-// column per block instead of a 16 KB tile per wave lets three blocks (twelve waves)
-// share a compute unit instead of two.
-constexpr int kShSeg = 33;               // rows per wave in the flush
-constexpr int kShRows = 4 * kShSeg;      // samples per sensor in the shared column
-constexpr int kShCap = 64;               // longest window kept in LDS (rows); longer ones go to the trace directly
+// transposed in place (each LDS row then holds SEG consecutive samples of one sensor, row
+// stride SEG: conflict-free both ways for odd SEG) and added to the global trace, two
+// sensors' runs of up to 32 samples per coalesced FP32 atomic (and the 33rd samples in
+// one more).  The column (4 SEG samples per sensor, 256 SEG bytes per sample row) and
+// the staged chunk take 50 KB for SEG = 33 (three blocks, twelve waves per compute unit)
+// or 39 KB for SEG = 23 (four blocks, sixteen waves), against 81 KB and two blocks for
+// forward_kernel's tile per wave.  (SEG = 15, five blocks, was slower: its 60-sample
+// column needs a second pass for too many chunks.)
 
-__global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
-    constexpr int NW = 4, G = 256;
-    __shared__ BallS sball[G];
+template <int SEG, int OCC>
+__global__ __launch_bounds__(256, OCC) void forward_shared_kernel(OpParams p) {
+    constexpr int NW = 4, G = 256, kShSeg = SEG, kShRows = 4 * SEG, kRun = SEG < 32 ? SEG : 32;
+    // longest window kept in LDS (rows; longer ones go to the trace directly), leaving every
+    // pass at least 16 first samples
+    constexpr int kShCap = kShRows - 16 < 64 ? kShRows - 16 : 64;
+    static_assert(SEG <= 33 && kShCap >= 16, "segment length");
+    __shared__ BallU sball[G];
     __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
     __shared__ float s_box[NW][8];                    // per wave of staged balls: tile box, amplitude sum, rows
     __shared__ __align__(16) uint32_t col[kShRows * 64];   // row k, sensor (lane): second differences
@@ -695,7 +733,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
         __syncthreads();
         {
             const BallF bl = stage_deform<SB_KERNEL_UNIFORM>(p, tid, nb, first, t, s_fb, nonfinite);
-            sball[tid] = ball_record<SB_KERNEL_UNIFORM>(p, bl, clipped);
+            sball[tid] = ball_record_u(p, bl, clipped);
             stage_box<kShCap>(bl, tid < nb, lane, s_box[wid]);
         }
         __syncthreads();
@@ -717,7 +755,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
             rmax = max(rmax, (int)s_box[w][7]);
         }
         const int nbw = max(0, min(64, nb - 64 * wid));   // this wave's balls: 64 wid + [0, nbw)
-        const BallS* const wb = sball + 64 * wid;
+        const BallU* const wb = sball + 64 * wid;
 
         // the item's sensor blocks (64 sensors each), one after the other
         const int sb_end = min(it.sblock + p.sb_per_item, p.n_sblocks);
@@ -757,7 +795,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
                 }
                 const bool qmode = __all(ok);             // the same in every wave (same sensors, same box)
                 bool bad = false;
-                auto setup = [&](const BallS& bs) { return pair_setup(p, bs, sx, sy, sz, active, bad); };
+                auto setup = [&](const BallU& bs) { return pair_setup(p, bs, sx, sy, sz, active, bad); };
 
                 // flush of the column after a pass (every wave, between block barriers): rows
                 // k0 .. k0 + 32 of every sensor, integrated, chained to the rows before, and added to
@@ -798,13 +836,14 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
                         const int kb = base + k0;         // trace sample of this sensor's row k0
                         s_kb[wid][lane] = kb;
                         wave_lds_sync();
-                        // atomic i adds samples kb + j, j < 32, of sensors 2i (lanes j) and 2i + 1
+                        // atomic i adds samples kb + j, j < kRun, of sensors 2i (lanes j) and 2i + 1
                         // (lanes 32 + j): one 32-bit byte offset per lane from the pair's row
                         const int half = lane >> 5, j = lane & 31;
+                        const bool jv = j < kRun;
                         const int nact = p.S - s0;        // sensors of the group inside the record's S
                         const bool inside = __all(!active || (kb >= 0 && kb <= p.T - kShSeg)) && p.T < (1 << 28);
                         const int* const kbv = &s_kb[wid][half];
-                        const float* const sv = seg + half * kShSeg + j;
+                        const float* const sv = seg + half * kShSeg + (jv ? j : 0);
                         if (inside) {
                             const uint32_t lane_b = (uint32_t)(half * p.T + j) * 4u;
 #pragma unroll 1
@@ -813,7 +852,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
                                 int kk[8];
 #pragma unroll
                                 for (int u = 0; u < 8; ++u) {
-                                    vv[u] = sv[2 * (i0 + u) * kShSeg];
+                                    vv[u] = jv ? sv[2 * (i0 + u) * kShSeg] : 0.f;
                                     kk[u] = kbv[2 * (i0 + u)];
                                 }
 #pragma unroll
@@ -826,7 +865,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
                         } else {
 #pragma unroll 1
                             for (int i = 0; i < 32; ++i) {
-                                const float vi = sv[2 * i * kShSeg];
+                                const float vi = jv ? sv[2 * i * kShSeg] : 0.f;
                                 const int a = 2 * i + half;
                                 const int k = kbv[2 * i] + j;
                                 if (vi != 0.f && a < nact) {
@@ -836,7 +875,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
                             }
                         }
                         // the 33rd sample of every sensor (lane = sensor)
-                        {
+                        if (kShSeg > 32) {
                             const float vl = seg[lane * kShSeg + 32];
                             const int k = kb + 32;
                             if (vl != 0.f && active) {
@@ -863,7 +902,7 @@ __global__ __launch_bounds__(256, 3) void forward_shared_kernel(OpParams p) {
                             // every ball of the wave; the next ball's FP64 set-up runs while this
                             // ball's seven LDS adds complete (as in forward_kernel)
                             FwdPair cur = setup(wb[0]);
-                            BallS bn = wb[min(1, nbw - 1)];
+                            BallU bn = wb[min(1, nbw - 1)];
                             for (int i = 0; i < nbw; ++i) {
                                 const bool part = cur.in_tile;
                                 const int rows = max(cur.W, 5) + 2;       // the same in every lane
@@ -961,7 +1000,12 @@ hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipS
         if (tc.nw != 1 || tc.g != 256) return hipErrorInvalidValue;   // sensor blocks of 64, chunks of 256
         const int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
         if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL(forward_shared_kernel, dim3((unsigned)grid), dim3(256), 0, st, p);
+        if (tc.ucap == 132)
+            hipLaunchKernelGGL((forward_shared_kernel<33, 3>), dim3((unsigned)grid), dim3(256), 0, st, p);
+        else if (tc.ucap == 92)
+            hipLaunchKernelGGL((forward_shared_kernel<23, 4>), dim3((unsigned)grid), dim3(256), 0, st, p);
+        else
+            return hipErrorInvalidValue;
         return hipGetLastError();
     }
     if (kernel == SB_KERNEL_UNIFORM) {

@@ -116,7 +116,8 @@ def test_last_error_is_per_call_message():
 def test_header_constants_match_binding():
     text = open(binding.HEADER).read()
     for name in ("SB_OK", "SB_ERR_INVALID_ARG", "SB_ERR_SHAPE", "SB_ERR_NONFINITE", "SB_ERR_HIP",
-                 "SB_ERR_DEVICE_FLAG", "SB_MAX_SCENES"):
+                 "SB_ERR_DEVICE_FLAG", "SB_MAX_SCENES", "SB_TUNE_FWD_COLUMN", "SB_FWD_COLUMN_SHARED",
+                 "SB_FWD_COLUMN_SHARED_SHORT"):
         import re
         m = re.search(rf"#define\s+{name}\s+\(?(-?\d+)\)?", text)
         assert m, name
@@ -131,8 +132,13 @@ def test_tuning_knobs_validate_and_round_trip():
     assert lib.slingbag_tune(binding.SB_TUNE_ADJ_ITEMS, 0) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, 64) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 256) == binding.SB_ERR_INVALID_ARG
+    assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 3) == binding.SB_ERR_INVALID_ARG
     saved = {k: binding.tune_get(k) for k in (1, 2, 3, 4)}
+    assert saved[binding.SB_TUNE_FWD_COLUMN] == binding.SB_FWD_COLUMN_SHARED_SHORT   # the default
     try:
+        for col in (64, 128, binding.SB_FWD_COLUMN_SHARED, binding.SB_FWD_COLUMN_SHARED_SHORT):
+            binding.tune(binding.SB_TUNE_FWD_COLUMN, col)
+            assert binding.tune_get(binding.SB_TUNE_FWD_COLUMN) == col
         binding.tune(binding.SB_TUNE_FWD_COLUMN, 64)
         binding.tune(binding.SB_TUNE_ADJ_OCCUPANCY, 3)
         binding.tune(binding.SB_TUNE_ADJ_ITEMS, 1234)

@@ -1,6 +1,7 @@
-"""GPU parity of the uniform sphere's shared-column forward (SB_TUNE_FWD_COLUMN =
-SB_FWD_COLUMN_SHARED): the forward cases of the parity suite, run again with that
-layout set.  Unsorted balls (every 256-ball chunk spans the whole cube) make each
+"""GPU parity of the uniform sphere's other forward column layouts: the forward cases of
+the parity suite, run again with SB_TUNE_FWD_COLUMN set to a wave's own 64-sample column
+and to the 132-sample shared column (the suite itself runs the default, the 92-sample
+shared column).  Unsorted balls (every 256-ball chunk spans the whole cube) make each
 sensor's arrivals spread over several columns, so they take the multi-pass path;
 sensors among the balls take the path without an integer scale."""
 
@@ -18,11 +19,11 @@ from test_gpu_parity import (plain, test_4d_fourier_small, test_ball_longer_than
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(autouse=True)
-def shared_column():
+@pytest.fixture(autouse=True, params=[64, 1], ids=["wave64", "shared132"])
+def shared_column(request):
     from paper_2412_03898_amd import binding
     saved = binding.tune_get(binding.SB_TUNE_FWD_COLUMN)
-    binding.tune(binding.SB_TUNE_FWD_COLUMN, binding.SB_FWD_COLUMN_SHARED)
+    binding.tune(binding.SB_TUNE_FWD_COLUMN, request.param)
     try:
         yield
     finally:

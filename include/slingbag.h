@@ -255,9 +255,12 @@ int slingbag_plan_destroy(sb_plan* plan);
  *                          with a 92-sample column; four blocks per compute unit, more
  *                          passes where a chunk's arrivals spread wider);
  *                          default SB_FWD_COLUMN_SHARED_SHORT
- *   SB_TUNE_FWD_GAUSS_COLUMN  forward LDS column length for the Gaussian ball: 128 samples
- *                          (blocks of 4 waves) or 256 (blocks of 2 waves, for windows that
- *                          nearly fill 128 rows); default 256
+ *   SB_TUNE_FWD_GAUSS_COLUMN  forward layout for the Gaussian ball: a column of 128 samples
+ *                          per wave and sensor (blocks of 4 waves) or 256 (blocks of 2 waves,
+ *                          for windows that nearly fill 128 rows), or SB_FWD_GAUSS_LANE (a
+ *                          lane per sample: each wave takes one sensor at a time and adds
+ *                          the windows to a 512-sample LDS row; sixteen waves per compute
+ *                          unit); default SB_FWD_GAUSS_LANE
  *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4;
  *                          default 4
  *   SB_TUNE_ADJ_ITEMS      adjoint work items the sensor split aims for: 1 .. 2^22;
@@ -269,6 +272,7 @@ int slingbag_plan_destroy(sb_plan* plan);
 #define SB_TUNE_FWD_GAUSS_COLUMN 4
 #define SB_FWD_COLUMN_SHARED        1   /* values of SB_TUNE_FWD_COLUMN */
 #define SB_FWD_COLUMN_SHARED_SHORT  2
+#define SB_FWD_GAUSS_LANE           1   /* value of SB_TUNE_FWD_GAUSS_COLUMN */
 int slingbag_tune(int key, int value);
 int slingbag_tune_get(int key, int* value);
 

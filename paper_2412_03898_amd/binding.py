@@ -244,6 +244,8 @@ SB_TUNE_FWD_COLUMN, SB_TUNE_ADJ_OCCUPANCY, SB_TUNE_ADJ_ITEMS, SB_TUNE_FWD_GAUSS_
 # SB_TUNE_FWD_COLUMN values besides 64 and 128: one column per sensor shared by a block's
 # waves, 132 samples (three blocks per compute unit) or 92 (four)
 SB_FWD_COLUMN_SHARED, SB_FWD_COLUMN_SHARED_SHORT = 1, 2
+# SB_TUNE_FWD_GAUSS_COLUMN value besides 128 and 256: a lane per sample, a row per wave
+SB_FWD_GAUSS_LANE = 1
 
 
 def tune(key: int, value: int):

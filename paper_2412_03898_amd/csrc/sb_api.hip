@@ -132,7 +132,8 @@ static int validate_batch(const sb_batch* batch, Shape& sh) {
 struct Tuning {
     int fwd_ucap = SB_FWD_COLUMN_SHARED_SHORT;   // uniform sphere: 64 or 128 samples per wave's LDS
                                                  // column, or one of the shared columns
-    int fwd_gauss_ucap = 256;  // 128 (4-wave blocks) or 256 (2-wave blocks): Gaussian ball
+    int fwd_gauss_ucap = SB_FWD_GAUSS_LANE;   // Gaussian ball: 128 (4-wave blocks), 256 (2-wave
+                                              // blocks) or a lane per sample
     int adj_occ = 4;           // 2, 3 or 4 blocks (waves per SIMD) per CU for the adjoint
     int adj_items = 8192;      // adjoint items the sensor split aims for
 };
@@ -154,12 +155,13 @@ static TileCfg pick_forward_tiles(int kernel, const Tuning& tu) {
     tc.nw = long_col ? 2 : 4;
     tc.g = 64 * tc.nw;
     tc.ucap = kernel == SB_KERNEL_UNIFORM ? tu.fwd_ucap : tu.fwd_gauss_ucap;
-    tc.shared = kernel == SB_KERNEL_UNIFORM &&
-                (tu.fwd_ucap == SB_FWD_COLUMN_SHARED || tu.fwd_ucap == SB_FWD_COLUMN_SHARED_SHORT);
+    tc.shared = kernel == SB_KERNEL_UNIFORM
+                    ? (tu.fwd_ucap == SB_FWD_COLUMN_SHARED || tu.fwd_ucap == SB_FWD_COLUMN_SHARED_SHORT)
+                    : tu.fwd_gauss_ucap == SB_FWD_GAUSS_LANE;
     if (tc.shared) {
-        tc.nw = 1;     // the block's four waves share each 64-sensor block
+        tc.nw = 1;     // 64-sensor blocks: the block's four waves share each of them
         tc.g = 256;
-        tc.ucap = tu.fwd_ucap == SB_FWD_COLUMN_SHARED_SHORT ? 92 : 132;   // samples per sensor
+        tc.ucap = kernel != SB_KERNEL_UNIFORM ? 512 : (tu.fwd_ucap == SB_FWD_COLUMN_SHARED_SHORT ? 92 : 132);
     }
     return tc;
 }
@@ -655,8 +657,8 @@ int slingbag_tune(int key, int value) {
             g_tune.fwd_ucap = value;
             return SB_OK;
         case SB_TUNE_FWD_GAUSS_COLUMN:
-            if (value != 128 && value != 256)
-                return fail(SB_ERR_INVALID_ARG, "Gaussian forward column must be 128 or 256");
+            if (value != 128 && value != 256 && value != SB_FWD_GAUSS_LANE)
+                return fail(SB_ERR_INVALID_ARG, "Gaussian forward column must be 128, 256 or SB_FWD_GAUSS_LANE");
             g_tune.fwd_gauss_ucap = value;
             return SB_OK;
         case SB_TUNE_ADJ_OCCUPANCY:
@@ -691,7 +693,7 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
     int& col_knob = uni ? cur.fwd_ucap : cur.fwd_gauss_ucap;
     int best_col = col_knob;
     for (int col : {64, 128, 256, SB_FWD_COLUMN_SHARED, SB_FWD_COLUMN_SHARED_SHORT}) {
-        if (uni ? col == 256 : (col != 128 && col != 256)) continue;
+        if (uni ? col == 256 : (col == 64 || col == SB_FWD_COLUMN_SHARED_SHORT)) continue;   // Gaussian: 128, 256, lane
         col_knob = col;
         set_tuning(cur);
         st = time_ms(s, reps, [&] { return slingbag_forward(cfg, batch, balls, deform, frame_t, sensors, signals, stream); }, &ms);

@@ -984,6 +984,195 @@ __global__ __launch_bounds__(256, OCC) void forward_shared_kernel(OpParams p) {
     if (nonfinite) raise_flag(p.flags, SB_FLAG_NONFINITE);
 }
 
+// ---- Gaussian ball, a lane per sample ------------------------------------------------
+//
+// A Gaussian ball's window is long (≈100 samples for the heart phantom's balls), so a
+// tile of 64 sensors needs some 256 rows per wave, and forward_kernel then fits one
+// two-wave block per compute unit.  Here a lane takes a sample instead: a wave walks its
+// sensors one at a time, and for each it first sets up the chunk's 256 pairs (lane = ball,
+// four rounds; results to a per-wave LDS table), then adds each ball's window to a
+// per-wave LDS row of the sensor's samples, 63 samples per step (one exponential per lane:
+// a sample's second boundary comes from the next lane; read, add, write: the row is the
+// wave's own), and finally adds the row to the global trace with coalesced FP32 atomics.  The row starts at the chunk's earliest window at that sensor; a window that
+// would leave it flushes the row and restarts it at that window, and a window longer than
+// the row goes to the trace directly (still 64 consecutive samples per atomic).  The
+// block (staged chunk, four tables and four rows) takes 37 KB: four blocks, sixteen
+// waves per compute unit.
+
+// The Gaussian ball's record (48 bytes; no inside test: any sensor off the centre).
+struct BallG {
+    double x, y, z;   // deformed centre (m)
+    double c1;        // t0 fs + h - 1/2, h = kGaussCut rho: the window starts at floor(r / delta - c1)
+    float amp;        // amplitude scale of the trace: P_f rho^2 delta / 2
+    float rhof;       // rho = a_f / delta (samples)
+    float hf;         // half-width h of the window
+    int Wc;           // window length W = floor(2 h) + 2; 0: no ball; -1: longer than any record
+};
+
+// A pair of the lane's ball with the wave's current sensor, as the window loop reads it.
+struct GPair {
+    int klo;          // sample index of sample 0; INT_MIN: no window
+    float xg;         // boundary 0: tau - k_lo + 1/2
+    float C;          // amplitude P_f rho^2 delta / (2 r)
+    float ce;         // exp2 scale -log2(e) / (2 rho^2)
+};
+
+constexpr int kGRow = 512;        // samples per wave's row
+
+__global__ __launch_bounds__(256, 4) void forward_gauss_lane_kernel(OpParams p) {
+    constexpr int NW = 4, G = 256;
+    __shared__ BallG sball[G];
+    __shared__ double s_fb[2 * SB_MAX_FOURIER];       // Fourier basis of the item's frame
+    __shared__ __align__(16) GPair s_pair[NW][G];     // per wave: the current sensor's pairs
+    __shared__ float s_row[NW][kGRow + 64];           // per wave: the current sensor's samples from `base`
+                                                      // (64 samples of padding: the last step of a
+                                                      // window adds zeros past its end)
+
+    const int tid = threadIdx.x, wid = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    float* const row = s_row[wid];
+    for (int k = lane; k < kGRow + 64; k += 64) row[k] = 0.f;
+    GPair* const tab = s_pair[wid];
+    bool clipped = false, geometry = false, nonfinite = false;
+
+    for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
+        const Item it = decode_item(p, item);
+        const Scene& sc = p.scenes[it.scene];
+        const int gf = sc.frame0 + it.frame;
+        const float t = p.frame_t[gf];
+        const int64_t first = sc.ball0 + (int64_t)it.group * G;
+        const int nb = min(G, sc.n_balls - it.group * G);
+        __syncthreads();   // the previous item is done with sball and s_fb
+        if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
+        __syncthreads();
+        {
+            BallF bl = stage_deform<SB_KERNEL_GAUSS>(p, tid, nb, first, t, s_fb, nonfinite);
+            BallG bs;
+            const bool valid = bl.rho >= 0.0;
+            const double h = (double)kGaussCut * bl.rho;
+            bs.x = bl.x;
+            bs.y = bl.y;
+            bs.z = bl.z;
+            bs.c1 = p.t0fs + h - 0.5;
+            bs.amp = bl.amp;
+            bs.rhof = bl.rhof;
+            bs.hf = (float)h;
+            bs.Wc = !valid ? 0 : (h >= 1.0e6 ? -1 : (int)(2.0 * h) + 2);
+            clipped |= valid && h >= 1.0e6;               // a window longer than any record
+            sball[tid] = bs;
+        }
+        __syncthreads();
+
+        // the wave's sensors of the item's 64-sensor blocks: 16 per block, one at a time
+        const int sb_end = min(it.sblock + p.sb_per_item, p.n_sblocks);
+        for (int sbk = it.sblock; sbk < sb_end; ++sbk) {
+            const int s_lo = sbk * 64 + wid * 16, s_hi = min(s_lo + 16, p.S);
+            for (int s = s_lo; s < s_hi; ++s) {
+                const double sx = p.sensors[s], sy = p.sensors[p.S + s], sz = p.sensors[2 * p.S + s];
+                float* const out_row = p.signals + ((int64_t)gf * p.S + s) * p.T;
+
+                // ---- set-up of the chunk's pairs with this sensor (lane = ball)
+                int kmin = INT_MAX, kend = INT_MIN;       // first sample and end of the row windows
+#pragma unroll
+                for (int r = 0; r < G / 64; ++r) {
+                    const int b = 64 * r + lane;
+                    const BallG bs = sball[b];
+                    GPair g;
+                    g.klo = INT_MIN;
+                    g.xg = 0.f;
+                    g.C = 0.f;
+                    g.ce = 0.f;
+                    if (b < nb && bs.Wc > 0) {
+                        float ri;
+                        const double dist = dist64(bs.x - sx, bs.y - sy, bs.z - sz, ri);
+                        const double u = fma(dist, p.inv_delta, -bs.c1);   // r / delta - t0 fs - h + 1/2
+                        const double kl = floor(u);
+                        const bool ok = dist > 0.0;
+                        geometry |= !ok;
+                        clipped |= ok && !(fabs(kl) < 5.0e8);
+                        if (ok && fabs(kl) < 5.0e8) {
+                            g.klo = (int)kl;
+                            g.xg = (float)(u - kl) + bs.hf;
+                            g.C = bs.amp * ri;
+                            g.ce = -1.4426950408889634f / (2.f * bs.rhof * bs.rhof);
+                            if (bs.Wc <= kGRow) {
+                                kmin = min(kmin, g.klo);
+                                kend = max(kend, g.klo + bs.Wc);
+                            }
+                        }
+                    }
+                    tab[b] = g;
+                }
+                int base = __builtin_amdgcn_readfirstlane(-wave_max_all(-max(kmin, -INT_MAX)));
+                const int kend_all = __builtin_amdgcn_readfirstlane(wave_max_all(kend));
+                // every row window of the chunk fits the row from `base` (the usual case)
+                const bool one_row = kend_all != INT_MIN && (int64_t)kend_all - base <= kGRow;
+                int kmax = one_row ? kend_all - base - 1 : -1;   // last row written
+                wave_lds_sync();
+
+                // adds the row (samples base .. base + kmax) to the trace and clears it
+                auto flush = [&]() {
+                    for (int k0 = 0; k0 <= kmax; k0 += 64) {
+                        const int k = k0 + lane;
+                        const float v = row[k];
+                        row[k] = 0.f;
+                        const int ks = base + k;
+                        if (v != 0.f) {
+                            if (ks >= 0 && ks < p.T) global_atomic_add(out_row + ks, v);
+                            else clipped = true;
+                        }
+                    }
+                    kmax = -1;
+                };
+
+                // ---- the windows, 64 samples per step (lane = sample)
+                for (int b = 0; b < nb; ++b) {
+                    const GPair g = tab[b];               // the same address in every lane
+                    const int klo = __builtin_amdgcn_readfirstlane(g.klo);
+                    if (klo == INT_MIN) continue;
+                    const int W = __builtin_amdgcn_readfirstlane(sball[b].Wc);
+                    if (W > kGRow) {
+                        // longer than the row: straight to the trace
+                        for (int j0 = 0; j0 < W; j0 += 64) {
+                            const int j = j0 + lane;
+                            const float x = g.xg - (float)j;
+                            const float v = g.C * (__builtin_amdgcn_exp2f((x - 1.f) * (x - 1.f) * g.ce) -
+                                                   __builtin_amdgcn_exp2f(x * x * g.ce));
+                            const int ks = klo + j;
+                            if (j < W && v != 0.f) {
+                                if (ks >= 0 && ks < p.T) global_atomic_add(out_row + ks, v);
+                                else clipped = true;
+                            }
+                        }
+                        continue;
+                    }
+                    int tl = klo - base;
+                    if (!one_row && (tl < 0 || tl + W > kGRow)) {
+                        flush();
+                        base = klo;
+                        tl = 0;
+                    }
+                    // 63 samples per step: lane i evaluates the Gaussian at boundary j0 + i, and
+                    // sample j0 + i (i < 63) takes the next boundary's value from lane i + 1
+                    for (int j0 = 0; j0 < W; j0 += 63) {
+                        const int j = j0 + lane;
+                        const float x = g.xg - (float)j;   // boundary j; sample j lies between j and j + 1
+                        const float E = __builtin_amdgcn_exp2f(x * x * g.ce);
+                        const float En = __builtin_bit_cast(
+                            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, E), 0x130, 0xF, 0xF, false));
+                        row[tl + j] += (lane < 63 && j < W) ? g.C * (En - E) : 0.f;   // tl + j < kGRow + 64
+                    }
+                    if (!one_row) kmax = max(kmax, tl + W - 1);
+                }
+                flush();
+                wave_lds_sync();                          // the table is read before the next sensor's set-up
+            }
+        }
+    }
+    if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
+    if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
+    if (nonfinite) raise_flag(p.flags, SB_FLAG_NONFINITE);
+}
+
 template <int NW, int G, int UCAP, int KERNEL>
 static hipError_t launch_fwd_t(const OpParams& p, hipStream_t st) {
     static_assert(G == 64 * NW, "one ball per thread in the sub-group compaction");
@@ -996,6 +1185,13 @@ static hipError_t launch_fwd_t(const OpParams& p, hipStream_t st) {
 
 hipError_t launch_forward(const OpParams& p, const TileCfg& tc, int kernel, hipStream_t st) {
     // the host's work decomposition (n_sblocks, n_groups) must match the instance
+    if (kernel == SB_KERNEL_GAUSS && tc.shared) {
+        if (tc.nw != 1 || tc.g != 256) return hipErrorInvalidValue;   // sensor blocks of 64, chunks of 256
+        const int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL(forward_gauss_lane_kernel, dim3((unsigned)grid), dim3(256), 0, st, p);
+        return hipGetLastError();
+    }
     if (kernel == SB_KERNEL_UNIFORM && tc.shared) {
         if (tc.nw != 1 || tc.g != 256) return hipErrorInvalidValue;   // sensor blocks of 64, chunks of 256
         const int64_t grid = p.n_items < (int64_t)(1 << 20) ? p.n_items : (int64_t)(1 << 20);

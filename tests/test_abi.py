@@ -117,7 +117,7 @@ def test_header_constants_match_binding():
     text = open(binding.HEADER).read()
     for name in ("SB_OK", "SB_ERR_INVALID_ARG", "SB_ERR_SHAPE", "SB_ERR_NONFINITE", "SB_ERR_HIP",
                  "SB_ERR_DEVICE_FLAG", "SB_MAX_SCENES", "SB_TUNE_FWD_COLUMN", "SB_FWD_COLUMN_SHARED",
-                 "SB_FWD_COLUMN_SHARED_SHORT"):
+                 "SB_FWD_COLUMN_SHARED_SHORT", "SB_FWD_GAUSS_LANE"):
         import re
         m = re.search(rf"#define\s+{name}\s+\(?(-?\d+)\)?", text)
         assert m, name
@@ -134,7 +134,8 @@ def test_tuning_knobs_validate_and_round_trip():
     assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 256) == binding.SB_ERR_INVALID_ARG
     assert lib.slingbag_tune(binding.SB_TUNE_FWD_COLUMN, 3) == binding.SB_ERR_INVALID_ARG
     saved = {k: binding.tune_get(k) for k in (1, 2, 3, 4)}
-    assert saved[binding.SB_TUNE_FWD_COLUMN] == binding.SB_FWD_COLUMN_SHARED_SHORT   # the default
+    assert saved[binding.SB_TUNE_FWD_COLUMN] == binding.SB_FWD_COLUMN_SHARED_SHORT   # the defaults
+    assert saved[binding.SB_TUNE_FWD_GAUSS_COLUMN] == binding.SB_FWD_GAUSS_LANE
     try:
         for col in (64, 128, binding.SB_FWD_COLUMN_SHARED, binding.SB_FWD_COLUMN_SHARED_SHORT):
             binding.tune(binding.SB_TUNE_FWD_COLUMN, col)
@@ -144,6 +145,8 @@ def test_tuning_knobs_validate_and_round_trip():
         binding.tune(binding.SB_TUNE_ADJ_ITEMS, 1234)
         binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, 128)
         assert tuple(binding.tune_get(k) for k in (1, 2, 3, 4)) == (64, 3, 1234, 128)
+        binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, binding.SB_FWD_GAUSS_LANE)
+        assert binding.tune_get(binding.SB_TUNE_FWD_GAUSS_COLUMN) == binding.SB_FWD_GAUSS_LANE
     finally:
         for k, v in saved.items():
             binding.tune(k, v)

@@ -603,7 +603,7 @@ def test_windows_longer_than_the_column(col):
     assert err <= SIG_TOL
 
 
-@pytest.mark.parametrize("col", [128, 256])
+@pytest.mark.parametrize("col", [128, 256, 1])     # 1: a lane per sample
 def test_gaussian_ball_both_columns(col):
     """Gaussian balls (Fourier 4D, windows of 20 to 125 samples) at both column lengths
     of their forward: 128 rows in blocks of four waves, 256 rows in blocks of two."""

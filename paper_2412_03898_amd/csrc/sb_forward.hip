@@ -1033,6 +1033,9 @@ __global__ __launch_bounds__(256, 4) void forward_gauss_lane_kernel(OpParams p) 
     for (int k = lane; k < kGRow + 64; k += 64) row[k] = 0.f;
     GPair* const tab = s_pair[wid];
     bool clipped = false, geometry = false, nonfinite = false;
+    // samples that fell outside the record, as a lane value (a flag carried as a lane mask
+    // through the window loops costs scalar mask updates in every block)
+    uint32_t clip_w = 0u;
 
     for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
         const Item it = decode_item(p, item);
@@ -1118,57 +1121,76 @@ __global__ __launch_bounds__(256, 4) void forward_gauss_lane_kernel(OpParams p) 
                         const int ks = base + k;
                         if (v != 0.f) {
                             if (ks >= 0 && ks < p.T) global_atomic_add(out_row + ks, v);
-                            else clipped = true;
+                            else clip_w = 1u;
                         }
                     }
                     kmax = -1;
                 };
 
-                // ---- the windows, 64 samples per step (lane = sample)
-                for (int b = 0; b < nb; ++b) {
-                    const GPair g = tab[b];               // the same address in every lane
-                    const int klo = __builtin_amdgcn_readfirstlane(g.klo);
-                    if (klo == INT_MIN) continue;
-                    const int W = __builtin_amdgcn_readfirstlane(sball[b].Wc);
-                    if (W > kGRow) {
-                        // longer than the row: straight to the trace
-                        for (int j0 = 0; j0 < W; j0 += 64) {
-                            const int j = j0 + lane;
-                            const float x = g.xg - (float)j;
-                            const float v = g.C * (__builtin_amdgcn_exp2f((x - 1.f) * (x - 1.f) * g.ce) -
-                                                   __builtin_amdgcn_exp2f(x * x * g.ce));
-                            const int ks = klo + j;
-                            if (j < W && v != 0.f) {
-                                if (ks >= 0 && ks < p.T) global_atomic_add(out_row + ks, v);
-                                else clipped = true;
-                            }
-                        }
-                        continue;
-                    }
-                    int tl = klo - base;
-                    if (!one_row && (tl < 0 || tl + W > kGRow)) {
-                        flush();
-                        base = klo;
-                        tl = 0;
-                    }
-                    // 63 samples per step: lane i evaluates the Gaussian at boundary j0 + i, and
-                    // sample j0 + i (i < 63) takes the next boundary's value from lane i + 1
-                    for (int j0 = 0; j0 < W; j0 += 63) {
+                // ---- the windows (lane = sample)
+                // a window longer than the row: straight to the trace, 64 samples per step
+                auto direct = [&](const GPair& g, int klo, int W) {
+                    for (int j0 = 0; j0 < W; j0 += 64) {
                         const int j = j0 + lane;
-                        const float x = g.xg - (float)j;   // boundary j; sample j lies between j and j + 1
+                        const float x = g.xg - (float)j;
+                        const float v = g.C * (__builtin_amdgcn_exp2f((x - 1.f) * (x - 1.f) * g.ce) -
+                                               __builtin_amdgcn_exp2f(x * x * g.ce));
+                        const int ks = klo + j;
+                        if (j < W && v != 0.f) {
+                            if (ks >= 0 && ks < p.T) global_atomic_add(out_row + ks, v);
+                            else clip_w = 1u;
+                        }
+                    }
+                };
+                // a window into the row from row sample tl on, 63 samples per step: lane i
+                // evaluates the Gaussian at boundary j0 + i, and sample j0 + i (i < 63) takes the
+                // next boundary's value from lane i + 1
+                auto to_row = [&](const GPair& g, int W, int tl) {
+                    float x = g.xg - (float)lane;         // boundary j0 + lane (exact: integer steps)
+                    for (int j0 = 0; j0 < W; j0 += 63) {
                         const float E = __builtin_amdgcn_exp2f(x * x * g.ce);
                         const float En = __builtin_bit_cast(
                             float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, E), 0x130, 0xF, 0xF, false));
-                        row[tl + j] += (lane < 63 && j < W) ? g.C * (En - E) : 0.f;   // tl + j < kGRow + 64
+                        const int n = min(63, W - j0);    // samples of this step
+                        row[tl + j0 + lane] += lane < n ? g.C * (En - E) : 0.f;   // < kGRow + 64
+                        x -= 63.f;
                     }
-                    if (!one_row) kmax = max(kmax, tl + W - 1);
+                };
+                if (one_row) {
+                    for (int b = 0; b < nb; ++b) {
+                        const GPair g = tab[b];           // the same address in every lane
+                        const int klo = __builtin_amdgcn_readfirstlane(g.klo);
+                        if (klo == INT_MIN) continue;
+                        const int W = __builtin_amdgcn_readfirstlane(sball[b].Wc);
+                        if (W > kGRow) direct(g, klo, W);
+                        else to_row(g, W, klo - base);
+                    }
+                } else {
+                    for (int b = 0; b < nb; ++b) {
+                        const GPair g = tab[b];
+                        const int klo = __builtin_amdgcn_readfirstlane(g.klo);
+                        if (klo == INT_MIN) continue;
+                        const int W = __builtin_amdgcn_readfirstlane(sball[b].Wc);
+                        if (W > kGRow) {
+                            direct(g, klo, W);
+                            continue;
+                        }
+                        int tl = klo - base;
+                        if (tl < 0 || tl + W > kGRow) {
+                            flush();
+                            base = klo;
+                            tl = 0;
+                        }
+                        to_row(g, W, tl);
+                        kmax = max(kmax, tl + W - 1);
+                    }
                 }
                 flush();
                 wave_lds_sync();                          // the table is read before the next sensor's set-up
             }
         }
     }
-    if (clipped) raise_flag(p.flags, SB_FLAG_CLIPPED);
+    if (clipped || clip_w) raise_flag(p.flags, SB_FLAG_CLIPPED);
     if (geometry) raise_flag(p.flags, SB_FLAG_GEOMETRY);
     if (nonfinite) raise_flag(p.flags, SB_FLAG_NONFINITE);
 }

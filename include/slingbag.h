@@ -261,8 +261,9 @@ int slingbag_plan_destroy(sb_plan* plan);
  *                          lane per sample: each wave takes one sensor at a time and adds
  *                          the windows to a 512-sample LDS row; sixteen waves per compute
  *                          unit); default SB_FWD_GAUSS_LANE
- *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4;
- *                          default 4
+ *   SB_TUNE_ADJ_OCCUPANCY  adjoint blocks per compute unit the compiler targets: 2, 3 or 4
+ *                          (both kernels; the Gaussian ball with the 2-harmonic Fourier
+ *                          series at most 3); default 4
  *   SB_TUNE_ADJ_ITEMS      adjoint work items the sensor split aims for: 1 .. 2^22;
  *                          default 8192
  * Unknown keys or values return SB_ERR_INVALID_ARG and change nothing. */

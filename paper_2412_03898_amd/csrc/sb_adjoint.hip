@@ -640,9 +640,11 @@ static hipError_t launch_adj_t(const OpParams& p, hipStream_t st) {
 
 template <int UROW, int OCC>
 static hipError_t launch_adj_m(const OpParams& p, hipStream_t st) {
-    // register accumulators for the Fourier coefficients when they fit (K <= 2)
+    // register accumulators for the Fourier coefficients when they fit (K <= 2); with them
+    // the kernel needs 168 registers, so it is held to three blocks per compute unit (at
+    // four it spills 55)
     const bool reg = p.basis == SB_BASIS_FOURIER && p.M == 4;
-    return reg ? launch_adj_t<UROW, 4, OCC>(p, st) : launch_adj_t<UROW, 0, OCC>(p, st);
+    return reg ? launch_adj_t<UROW, 4, (OCC > 3 ? 3 : OCC)>(p, st) : launch_adj_t<UROW, 0, OCC>(p, st);
 }
 
 // Second phase of the two-phase chain rule: one thread per ball.  From the summed
@@ -741,7 +743,11 @@ hipError_t launch_adjoint(const OpParams& p, const TileCfg& tc, int kernel, hipS
         if (tc.nw == 3) return launch_adj_um<3>(p, st);
         if (tc.nw == 4) return launch_adj_um<4>(p, st);
     }
-    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 384 && tc.nw == 2) return launch_adj_m<384, 2>(p, st);
+    if (kernel == SB_KERNEL_GAUSS && tc.ucap == 384) {
+        if (tc.nw == 2) return launch_adj_m<384, 2>(p, st);
+        if (tc.nw == 3) return launch_adj_m<384, 3>(p, st);
+        if (tc.nw == 4) return launch_adj_m<384, 4>(p, st);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -168,7 +168,7 @@ static TileCfg pick_forward_tiles(int kernel, const Tuning& tu) {
 
 static TileCfg pick_adjoint_tiles(int kernel, const Tuning& tu) {
     TileCfg tc;
-    tc.nw = kernel == SB_KERNEL_UNIFORM ? tu.adj_occ : 2;
+    tc.nw = tu.adj_occ;
     tc.g = 256;
     tc.ucap = kernel == SB_KERNEL_UNIFORM ? 128 : 384;
     return tc;
@@ -709,7 +709,6 @@ int slingbag_autotune(const sb_config* cfg, const sb_batch* batch, const float* 
     int best_occ = cur.adj_occ, best_items = cur.adj_items;
     for (int occ : {2, 3, 4}) {
         for (int items : {2048, 4096, 8192, 16384}) {
-            if (cfg->kernel != SB_KERNEL_UNIFORM && occ != 2) continue;
             cur.adj_occ = occ;
             cur.adj_items = items;
             set_tuning(cur);

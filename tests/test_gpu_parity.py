@@ -629,3 +629,33 @@ def test_gaussian_ball_both_columns(col):
     _say(f"gaussian column {col}: forward rel-L2 {err:.3e} flags={flags}")
     assert flags == 0
     assert err <= SIG_TOL
+
+
+@pytest.mark.parametrize("col", [1, 256])     # 1: a lane per sample
+def test_gaussian_ball_spread_chunks_and_windows_longer_than_the_row(col):
+    """Gaussian balls in random order over a 20 mm cube (every 256-ball chunk spreads its
+    arrivals at a sensor over ≈900 samples, more than the lane layout's 512-sample row, so
+    the row is flushed and restarted) and a few balls whose windows exceed the row (520 to
+    700 samples: added to the trace directly), against the oracle."""
+    from paper_2412_03898_amd import binding
+    wl = tiny_scene(n_balls=700, n_sensors=70, n_frames=2, kernel=1, basis=1, seed=91)
+    b = wl.balls.copy()
+    rng = np.random.default_rng(91)
+    delta = wl.c / wl.fs
+    big = rng.choice(b.shape[1], size=6, replace=False)
+    W = rng.integers(520, 701, size=big.size)
+    b[3, big] = ((W - 2 + 0.5) * delta / (2 * 6.0)).astype(np.float32)    # W = floor(12 rho) + 2
+    k0 = synth.record_start(0.060, 0.010, float(b[3].max()) * 12 * 1.1, 0.5e-3)
+    n = synth.record_length_needed(0.060, 0.010, float(b[3].max()) * 12 * 1.1, 0.5e-3, k0)
+    wl = with_(wl, balls=b, t0=k0 / wl.fs, n_samples=n)               # unsorted on purpose
+    saved = binding.tune_get(binding.SB_TUNE_FWD_GAUSS_COLUMN)
+    try:
+        binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, col)
+        y, flags = gpu_forward(wl)
+    finally:
+        binding.tune(binding.SB_TUNE_FWD_GAUSS_COLUMN, saved)
+    ref = oracle.forward(wl)
+    err = rel_l2(y, ref)
+    _say(f"gaussian spread chunks, long windows (column {col}): rel-L2 {err:.3e} flags={flags}")
+    assert flags == 0
+    assert err <= SIG_TOL

@@ -175,7 +175,9 @@ __device__ inline D2Win d2_window(int W, float x0, float rho, float Cs) {
     };
     auto qn = [](float v) { return (uint32_t)round_rpi(v); };
     const int Wp = LONG ? W : max(W, 5);
-    const float q1 = sq(x0 - 1.f);
+    // W >= 5 means rho >= 3/2: boundaries 1 and W - 2 then lie inside [-rho, rho] (x0 is in
+    // [rho, rho + 1), and W - 2 <= 2 rho), so their squares need no clamp
+    const float q1 = LONG ? (x0 - 1.f) * (x0 - 1.f) : sq(x0 - 1.f);
     float va, vb;                                        // sample 1 and the step to sample 2 (units of C)
     if (LONG || W >= 5) {
         va = fmaf(2.f, x0, -3.f);                        // C (2 x_1 - 1)
@@ -186,7 +188,7 @@ __device__ inline D2Win d2_window(int W, float x0, float rho, float Cs) {
         vb = (q2 - q3) - va;
     }
     const float xa = x0 - (float)(Wp - 2);               // boundary Wp-2 (exact in FP32)
-    const float qa = sq(xa), qb = sq(xa - 1.f);          // boundary Wp lies below -rho
+    const float qa = LONG ? xa * xa : sq(xa), qb = sq(xa - 1.f);   // boundary Wp lies below -rho
     const uint32_t u0 = qn(Cs * (rr - q1)), a = qn(Cs * va), b = qn(Cs * vb);
     const uint32_t e1 = qn(Cs * (qa - qb)), e2 = qn(Cs * (qb - rr));
     const uint32_t last = a + b * (uint32_t)(Wp - 4);    // ramp sample Wp-3

@@ -692,8 +692,8 @@ __global__ __launch_bounds__(64 * NW) void forward_kernel(OpParams p) {
 // transposed in place (each LDS row then holds SEG consecutive samples of one sensor, row
 // stride SEG: conflict-free both ways for odd SEG) and added to the global trace, two
 // sensors' runs of up to 32 samples per coalesced FP32 atomic (and the 33rd samples in
-// one more).  The column (4 SEG samples per sensor, 256 SEG bytes per sample row) and
-// the staged chunk take 50 KB for SEG = 33 (three blocks, twelve waves per compute unit)
+// one more).  The column (4 SEG rows of 64 sensors: 1 KB per unit of SEG) and the
+// staged chunk take 50 KB for SEG = 33 (three blocks, twelve waves per compute unit)
 // or 39 KB for SEG = 23 (four blocks, sixteen waves), against 81 KB and two blocks for
 // forward_kernel's tile per wave.  (SEG = 15, five blocks, was slower: its 60-sample
 // column needs a second pass for too many chunks.)

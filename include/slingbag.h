@@ -188,7 +188,7 @@ int slingbag_adjoint(const sb_config* cfg, const sb_batch* batch,
  * group neighbours into short arrival windows and the adjoint stage compact
  * residual rows.  Apply perm to every per-ball array (balls, deform,
  * optimiser state) with slingbag_permute.  Scratch: a per-device buffer
- * (keys, indices and radix-sort storage, about 24 bytes per ball), allocated
+ * (keys, indices and radix-sort tables, about 21 bytes per ball), allocated
  * on first use and grown as needed.  B_total must be below 2^31. */
 int slingbag_order(const sb_batch* batch, const float* balls, int32_t* perm, void* stream);
 

@@ -604,12 +604,10 @@ int slingbag_order(const sb_batch* batch, const float* balls, int32_t* perm, voi
     if ((st = device_state(&ds))) return st;
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)sh.B;
-    size_t temp_bytes = 0;
-    hipError_t e = sort_pairs(nullptr, temp_bytes, nullptr, nullptr, nullptr, nullptr, n, s);
-    if (e != hipSuccess) return hip_fail(e, "radix sort sizing");
     const size_t keys_bytes = ((size_t)n * 8 + 255) & ~(size_t)255;
     const size_t idx_bytes = ((size_t)n * 4 + 255) & ~(size_t)255;
-    const size_t need = 2 * keys_bytes + idx_bytes + temp_bytes + 256;
+    const size_t need = 2 * keys_bytes + idx_bytes + radix_sort_scratch_bytes(n);
+    hipError_t e = hipSuccess;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         if (ds->order_bytes < need) {
@@ -625,13 +623,15 @@ int slingbag_order(const sb_batch* batch, const float* balls, int32_t* perm, voi
             ds->order_bytes = need;
         }
     }
+    // keys, their ping-pong copy, the indices' ping-pong copy (the indices start
+    // in perm, where the sort leaves them), the radix tables
     char* base = (char*)ds->order_buf;
-    unsigned long long* kin = (unsigned long long*)base;
-    unsigned long long* kout = (unsigned long long*)(base + keys_bytes);
-    int* idx = (int*)(base + 2 * keys_bytes);
-    void* temp = base + 2 * keys_bytes + idx_bytes;
-    e = launch_morton_keys(balls, sh.B, batch->ball_offset, batch->n_scenes, kin, idx, s);
-    if (e == hipSuccess) e = sort_pairs(temp, temp_bytes, kin, kout, idx, (int*)perm, n, s);
+    unsigned long long* keys = (unsigned long long*)base;
+    unsigned long long* keys_tmp = (unsigned long long*)(base + keys_bytes);
+    int* idx_tmp = (int*)(base + 2 * keys_bytes);
+    void* tables = base + 2 * keys_bytes + idx_bytes;
+    e = launch_morton_keys(balls, sh.B, batch->ball_offset, batch->n_scenes, keys, (int*)perm, s);
+    if (e == hipSuccess) e = radix_sort_pairs(keys, keys_tmp, (int*)perm, idx_tmp, tables, n, s);
     if (e != hipSuccess) return hip_fail(e, "ordering kernels");
     return SB_OK;
 }

@@ -323,8 +323,12 @@ bool adjoint_two_phase(const OpParams& p);     // does launch_adjoint need OpPar
 hipError_t launch_chain_rule(const OpParams& p, hipStream_t st);
 hipError_t launch_morton_keys(const float* balls, int64_t B, const int64_t* ball_offset_host,
                               int n_scenes, unsigned long long* keys, int* idx, hipStream_t st);
-hipError_t sort_pairs(void* temp, size_t& temp_bytes, const unsigned long long* kin,
-                      unsigned long long* kout, const int* vin, int* vout, int n, hipStream_t st);
+// Stable sort of (key, value) pairs by the low 62 key bits; the result lands back
+// in keys / vals, keys_tmp and vals_tmp hold n elements each, scratch holds
+// radix_sort_scratch_bytes(n).
+size_t radix_sort_scratch_bytes(int n);
+hipError_t radix_sort_pairs(unsigned long long* keys, unsigned long long* keys_tmp, int* vals, int* vals_tmp,
+                            void* scratch, int n, hipStream_t st);
 hipError_t launch_gather_rows(const float* src, float* dst, int64_t rows, int64_t B, const int* perm,
                               hipStream_t st);
 hipError_t launch_fill(float* ptr, int64_t n, float v, hipStream_t st);

@@ -513,6 +513,35 @@ def test_order_matches_morton_definition():
     np.testing.assert_array_equal(nb, balls[:, perm])
 
 
+@pytest.mark.parametrize("sizes", [[1], [5, 4096, 4097], [1_100_000], [300] * 32],
+                         ids=["one", "ragged", "two-scan-groups", "32-scenes"])
+def test_order_ties_clamps_and_sizes(sizes):
+    """Stable order with many equal keys (balls sharing a grid cell, balls clamped to the
+    grid's faces), ragged tile counts, a table of more than 256 tiles (the column scan in
+    two groups) and the largest scene index; bit-exact against the numpy definition."""
+    import torch
+    from paper_2412_03898_amd import ops
+    rng = np.random.default_rng(sum(sizes) + len(sizes))
+    B = int(sum(sizes))
+    pos = rng.uniform(-0.01, 0.01, size=(3, B))
+    pos[:, ::3] = 0.004                                        # one shared cell
+    pos[:, 1::7] = rng.choice([-3.0, 2.5], size=(3, len(range(1, B, 7))))   # outside the grid
+    pos[:, 2::5] = np.round(pos[:, 2::5], 4)                   # a few hundred shared cells
+    balls = np.zeros((5, B), np.float32)
+    balls[:3] = pos
+    balls[3] = 2e-4
+    balls[4] = 1.0
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    base = synth.workload_plain(n_balls=4, n_sensors=4)
+    wl = with_(base, balls=balls, ball_offset=off, frame_offset=np.arange(len(sizes) + 1),
+               frame_t=np.zeros(len(sizes), np.float32))
+    _say(f"order B={B} scenes={len(sizes)}")
+    pb = ops.Problem.from_workload(wl)
+    perm = ops.order(pb, torch.from_numpy(balls).cuda()).cpu().numpy()
+    ref = np.concatenate([synth.morton_order(balls[:, a:b]) + a for a, b in zip(off[:-1], off[1:])])
+    np.testing.assert_array_equal(perm, ref)
+
+
 def test_result_independent_of_order():
     """Forward and gradients of a 4D scene are the same (up to the permutation) in any ball order."""
     wl = synth.workload_vessel_4d(n_balls=3000, n_sensors=70, n_frames=3)

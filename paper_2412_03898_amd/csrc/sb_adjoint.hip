@@ -319,9 +319,16 @@ __global__ __launch_bounds__(256, OCC) void adjoint_gauss_kernel(OpParams p) {
 // double-buffered, so one barrier per four sensors suffices.
 constexpr int kPfxRow = 128;      // staged residual samples per sensor
 
+// A sensor of the work item's split, with the row origin of the current frame.
+struct SensorRow {
+    double x, y, z;
+    int org;
+    int pad;
+};
+
 struct PfxSlot {
     double2 pfx[kPfxRow + 1];     // (P0[k], P1[k]), k = 0..kPfxRow
-    float rowf[kPfxRow];
+    double rowd[kPfxRow];         // the samples, widened once here rather than per pair
 };
 
 // Inclusive prefix sum over the 64 lanes of a wave (every lane active): row
@@ -347,7 +354,7 @@ __device__ inline double wave_incl_scan(double v) {
 // Stage one sensor's residual row: lane l holds samples o + 2l and o + 2l + 1.
 __device__ inline void stage_prefix(PfxSlot& sl, float e0, float e1, int lane) {
     const int i0 = 2 * lane;
-    *reinterpret_cast<float2*>(&sl.rowf[i0]) = make_float2(e0, e1);
+    *reinterpret_cast<double2*>(&sl.rowd[i0]) = make_double2((double)e0, (double)e1);
     const double s0 = (double)e0 + (double)e1;
     const double s1 = (double)i0 * (double)e0 + (double)(i0 + 1) * (double)e1;
     const double I0 = wave_incl_scan(s0), I1 = wave_incl_scan(s1);
@@ -361,8 +368,7 @@ template <int MREG, int OCC>
 __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
     static_assert(kPfxRow == 128, "two samples per lane");
     __shared__ PfxSlot slots[2][4];
-    __shared__ double s_sx[kAdjMaxSplit], s_sy[kAdjMaxSplit], s_sz[kAdjMaxSplit];   // sensors of the split
-    __shared__ int s_org[kAdjMaxSplit];
+    __shared__ SensorRow s_sen[kAdjMaxSplit];          // sensors of the split, row origins
     __shared__ double s_fb[2 * SB_MAX_FOURIER];
     __shared__ float s_red[4][8];
 
@@ -383,9 +389,9 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
 
         __syncthreads();                 // the previous item is done with the sensor arrays
         for (int j = tid; j < ns; j += 256) {
-            s_sx[j] = p.sensors[s_begin + j];
-            s_sy[j] = p.sensors[p.S + s_begin + j];
-            s_sz[j] = p.sensors[2 * p.S + s_begin + j];
+            s_sen[j].x = p.sensors[s_begin + j];
+            s_sen[j].y = p.sensors[p.S + s_begin + j];
+            s_sen[j].z = p.sensors[2 * p.S + s_begin + j];
         }
 
         float gb[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
         for (int f = 0; f < sc.n_frames; ++f) {
             const int gf = sc.frame0 + f;
             const float t = p.frame_t[gf];
-            __syncthreads();             // the previous frame is done with s_fb, s_org, slots
+            __syncthreads();             // the previous frame is done with s_fb, the row origins, slots
             if (p.basis == SB_BASIS_FOURIER && wid == 0) fourier_basis_lanes(t, p.n_terms, s_fb, lane);
             __syncthreads();
             BallF bl;
@@ -430,9 +436,9 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
             // row origins: every window of the chunk starts at or after o + 1
             for (int j = tid; j < ns; j += 256) {
                 double dmin, dmax;
-                box_distance_range(lo, hi, s_sx[j], s_sy[j], s_sz[j], dmin, dmax);
+                box_distance_range(lo, hi, s_sen[j].x, s_sen[j].y, s_sen[j].z, dmin, dmax);
                 const double ofl = floor(dmin * p.inv_delta - p.t0fs - hmax - 1.0) - 1.0;
-                s_org[j] = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
+                s_sen[j].org = (int)fmin(fmax(ofl, -5.0e8), 5.0e8);
             }
             __syncthreads();
 
@@ -440,15 +446,20 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
             const float rho = live ? bl.rhof : 0.f;
             const double rhod = live ? bl.rho : 0.0;
             const double c1 = p.t0fs + (rhod - 0.5);          // window start: floor(r / delta - c1)
-            const float nrr = -rho * rho, two_inv_delta = 2.f * inv_delta_f;
+            const double nrr = -rhod * rhod;
             const double r_in = rhod * (double)delta;          // sensor must be farther than this
             const bool w_ok = live && rhod < 1.0e6;
             const int W = w_ok ? (int)(2.0 * rhod) + 2 : 0;
+            // a window lies in the staged row iff 0 <= k_lo - o <= kPfxRow - W
+            const bool w_fits = W <= kPfxRow;
+            const int row_span = w_fits ? kPfxRow - W : 0;
             const float* res_frame = p.residual + (int64_t)gf * p.S * p.T;
-            float g5[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            // per-pair sums in FP64: the pair's offsets and closed forms are FP64
+            // already, so no conversion is spent on them
+            double h5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
             auto load_pair = [&](int j, float& e0, float& e1) {
-                const int k = s_org[j] + 2 * lane;
+                const int k = s_sen[j].org + 2 * lane;
                 const float* rr = res_frame + (int64_t)(s_begin + j) * p.T;
                 e0 = (k >= 0 && k < p.T) ? rr[k] : 0.f;
                 e1 = (k + 1 >= 0 && k + 1 < p.T) ? rr[k + 1] : 0.f;
@@ -465,37 +476,39 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                 for (int u = 0; u < nu; ++u) {
                     const int j = 4 * g + u;
                     const PfxSlot& sl = slots[buf][u];
-                    const double dx = bl.x - s_sx[j];
-                    const double dy = bl.y - s_sy[j];
-                    const double dz = bl.z - s_sz[j];
+                    const SensorRow sen = s_sen[j];
+                    const double dx = bl.x - sen.x;
+                    const double dy = bl.y - sen.y;
+                    const double dz = bl.z - sen.z;
                     float inv_r;
                     const double r = dist64(dx, dy, dz, inv_r);
                     const double uw = fma(r, p.inv_delta, -c1);    // tau - rho + 1/2
                     const double kl = floor(uw);
                     const double a0d = (uw - kl) + rhod;             // x_0 = tau - k_lo + 1/2
+                    const double x1 = a0d - 1.0;
                     const bool geo = w_ok && r > r_in;
                     geometry |= w_ok && !geo;
                     const bool use = geo && fabs(kl) < 5.0e8;
                     const int klo = use ? (int)kl : 0;
-                    const int tl = klo - s_org[j];
-                    const bool in_row = use && tl >= 0 && tl + W <= kPfxRow;
-                    // inside boundaries m = 1..M (M decided in FP64)
-                    const int M = use ? (int)ceil(a0d + rhod) - 1 : 0;
+                    const int tl = klo - sen.org;
+                    const bool in_row = use && w_fits && (unsigned)tl <= (unsigned)row_span;
+                    // inside boundaries m = 1..M, M = ceil(x_1 + rho) (decided in FP64)
+                    const int M = use ? (int)ceil(x1 + rhod) : 0;
                     // prefix form (lanes outside the row read row entry 0 and discard it);
                     // byte offsets from the slot base keep the address arithmetic to shifts
                     const int t0 = in_row ? tl : 0, iM = in_row ? tl + M : 0;
                     const char* const slb = reinterpret_cast<const char*>(&sl);
-                    constexpr int kRowOff = (int)offsetof(PfxSlot, rowf);
-                    const float r0 = *reinterpret_cast<const float*>(slb + kRowOff + (t0 << 2));
-                    const float rM = *reinterpret_cast<const float*>(slb + kRowOff + (iM << 2));
+                    constexpr int kRowOff = (int)offsetof(PfxSlot, rowd);
+                    const double r0 = *reinterpret_cast<const double*>(slb + kRowOff + (t0 << 3));
+                    const double rM = *reinterpret_cast<const double*>(slb + kRowOff + (iM << 3));
                     const double2 pa = *reinterpret_cast<const double2*>(slb + ((t0 + 1) << 4));
                     const double2 pb = *reinterpret_cast<const double2*>(slb + (iM << 4));
                     const double T0 = pb.x - pa.x;
                     const double T1 = (pb.y - pa.y) - (double)t0 * T0;
-                    const double xM = a0d - (double)M, x1 = a0d - 1.0;
-                    double St = fma(xM, (double)rM, fma(-x1, (double)r0, T0));
-                    double Sw = fma(xM * xM, (double)rM, fma(-x1 * x1, (double)r0, fma(2.0 * a0d - 1.0, T0, -2.0 * T1)));
-                    float Sr = rM - r0;
+                    const double xM = a0d - (double)M;
+                    double St = fma(xM, rM, fma(-x1, r0, T0));
+                    double Sw = fma(xM * xM, rM, fma(-x1 * x1, r0, fma(2.0 * a0d - 1.0, T0, -2.0 * T1)));
+                    double Sr = rM - r0;
                     // windows outside the staged row: boundaries straight from global memory
                     // (a window without an inside boundary, M < 1, contributes nothing and is
                     // skipped below)
@@ -551,36 +564,36 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                                     }
                                 }
                             }
-                            const double xMg = a0d - (double)M, x1g = a0d - 1.0;
-                            St = fma(xMg, (double)qM, fma(-x1g, (double)q0, g0));
-                            Sw = fma(xMg * xMg, (double)qM, fma(-x1g * x1g, (double)q0, fma(2.0 * a0d - 1.0, g0, -2.0 * g1)));
-                            Sr = qM - q0;
+                            St = fma(xM, (double)qM, fma(-x1, (double)q0, g0));
+                            Sw = fma(xM * xM, (double)qM, fma(-x1 * x1, (double)q0, fma(2.0 * a0d - 1.0, g0, -2.0 * g1)));
+                            Sr = (double)qM - (double)q0;
                         }
                     }
                     if (M >= 1) {                                // implies use
                         // C = P_f delta / (4 r); constant factors (P_f delta / 4, -2 rho / delta,
                         // delta / 4) are applied once per frame below
-                        const float A = fmaf(nrr, Sr, (float)Sw);
-                        const float Bs = (float)St;
-                        const float q = two_inv_delta * Bs - A * inv_r;   // dL/dr / (C)
-                        const float qr = q * inv_r * inv_r;                      // times 1/r for the direction
-                        g5[0] = fmaf(qr, (float)dx, g5[0]);
-                        g5[1] = fmaf(qr, (float)dy, g5[1]);
-                        g5[2] = fmaf(qr, (float)dz, g5[2]);
-                        g5[3] = fmaf(inv_r, Sr, g5[3]);
-                        g5[4] = fmaf(inv_r, A, g5[4]);
+                        const double ri = (double)inv_r;
+                        const double A = fma(nrr, Sr, Sw);
+                        const double q = fma(p.two_inv_delta, St, -A * ri);   // dL/dr / (C)
+                        const double qr = q * ri * ri;                       // times 1/r for the direction
+                        h5[0] = fma(qr, dx, h5[0]);
+                        h5[1] = fma(qr, dy, h5[1]);
+                        h5[2] = fma(qr, dz, h5[2]);
+                        h5[3] = fma(ri, Sr, h5[3]);
+                        h5[4] = fma(ri, A, h5[4]);
                     }
                 }
             }
             // per-frame factors of the accumulated sums: dL/dx_f = (P_f delta/4) sum q dx/r^2,
             // dL/dR_f = -(2 rho/delta)(P_f delta/4) sum Sr/r, dL/dP_f = (delta/4) sum A/r
+            float g5[5];
             {
                 const float cp = live ? bl.amp * delta * 0.25f : 0.f;
-                g5[0] *= cp;
-                g5[1] *= cp;
-                g5[2] *= cp;
-                g5[3] *= -2.f * rho * inv_delta_f * cp;
-                g5[4] *= delta * 0.25f;
+                g5[0] = (float)h5[0] * cp;
+                g5[1] = (float)h5[1] * cp;
+                g5[2] = (float)h5[2] * cp;
+                g5[3] = (float)h5[3] * (-2.f * rho * inv_delta_f * cp);
+                g5[4] = (float)h5[4] * (delta * 0.25f);
             }
             // chain rule through Eq. 1 (and Eq. 2 / the Fourier series) for this frame, or
             // (two-phase) this split's share of dL/d(deformed attributes) to the scratch

@@ -184,6 +184,7 @@ static void fill_common(OpParams& p, const sb_config* cfg, const sb_batch* batch
     p.n_terms = cfg->basis == SB_BASIS_STATIC ? 0 : cfg->n_terms;
     p.M = sh.M;
     p.inv_delta = cfg->fs / cfg->c;
+    p.two_inv_delta = 2.0 * p.inv_delta;
     p.t0fs = cfg->t0 * cfg->fs;
     p.delta = (float)(cfg->c / cfg->fs);
     p.n_scenes = batch->n_scenes;
@@ -577,6 +578,7 @@ int slingbag_voxelize(const sb_config* cfg, const sb_grid* grid, int64_t n_balls
     p.n_terms = cfg->basis == SB_BASIS_STATIC ? 0 : cfg->n_terms;
     p.M = (int32_t)M;
     p.inv_delta = 1.0;           // deform_ball then returns the size in metres
+    p.two_inv_delta = 2.0;
     e = launch_voxelize(p, cfg->kernel, grid->nx, grid->ny, grid->nz, grid->x0, grid->y0, grid->z0, grid->h, t,
                         volume, s);
     if (e != hipSuccess) return hip_fail(e, "voxelize kernel");

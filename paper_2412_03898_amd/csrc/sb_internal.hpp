@@ -42,6 +42,7 @@ struct OpParams {
     int64_t B;               // total balls (row stride of balls/deform)
     int64_t n_items;
     double inv_delta;        // fs / c   (samples per metre)
+    double two_inv_delta;    // 2 fs / c
     double t0fs;             // t0 * fs  (sample index of the time origin)
     float delta;             // c / fs   (metres per sample)
     int32_t S, T;

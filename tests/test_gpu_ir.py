@@ -58,9 +58,12 @@ def test_ir_checkpoint_resume(tmp_path):
     # FP32 atomics make runs differ at rounding level only
     np.testing.assert_allclose(lb + lc, la, rtol=1e-5)
     # The gradients are summed with FP32 atomics whose order varies between runs, so two
-    # runs agree only to that rounding; Adam's normalised step carries it into the
-    # parameters at about 1e-6 of their norm over these iterations.
-    for x, y, tol in ((c.balls, a.balls, 1e-5), (c.deform, a.deform, 1e-4)):
+    # runs agree only to that rounding, which Adam's normalised step carries into the
+    # parameters.  Two uninterrupted runs of this problem differ by up to 6e-9 of the
+    # balls' norm and 5e-5 of the coefficients' norm (the coefficients start at zero, so
+    # their norm is small beside that rounding); a checkpoint that lost the optimiser
+    # state would put the coefficients a whole Adam step apart, of the order of their norm.
+    for x, y, tol in ((c.balls, a.balls, 1e-5), (c.deform, a.deform, 5e-4)):
         x, y = x.cpu().numpy(), y.cpu().numpy()
         assert np.linalg.norm(x - y) <= tol * np.linalg.norm(y)
 

@@ -513,12 +513,13 @@ def test_order_matches_morton_definition():
     np.testing.assert_array_equal(nb, balls[:, perm])
 
 
-@pytest.mark.parametrize("sizes", [[1], [5, 4096, 4097], [1_100_000], [300] * 32],
-                         ids=["one", "ragged", "two-scan-groups", "32-scenes"])
+@pytest.mark.parametrize("sizes", [[1], [5, 4096, 4097], [1_100_000], [300] * 32, [0, 300, 0, 5000, 0]],
+                         ids=["one", "ragged", "two-scan-groups", "32-scenes", "empty-scenes"])
 def test_order_ties_clamps_and_sizes(sizes):
     """Stable order with many equal keys (balls sharing a grid cell, balls clamped to the
     grid's faces), ragged tile counts, a table of more than 256 tiles (the column scan in
-    two groups) and the largest scene index; bit-exact against the numpy definition."""
+    two groups), the largest scene index and empty scenes; bit-exact against the numpy
+    definition."""
     import torch
     from paper_2412_03898_amd import ops
     rng = np.random.default_rng(sum(sizes) + len(sizes))

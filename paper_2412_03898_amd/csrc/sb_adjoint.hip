@@ -467,6 +467,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
             float e0 = 0.f, e1 = 0.f;
             if (wid < ns) load_pair(wid, e0, e1);
             const int ngroups = (ns + 3) >> 2;
+            SensorRow sen_next = s_sen[0];       // the next pair's sensor, read one pair ahead
             for (int g = 0; g < ngroups; ++g) {
                 const int buf = g & 1;
                 if (4 * g + wid < ns) stage_prefix(slots[buf][wid], e0, e1, lane);
@@ -476,7 +477,8 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
                 for (int u = 0; u < nu; ++u) {
                     const int j = 4 * g + u;
                     const PfxSlot& sl = slots[buf][u];
-                    const SensorRow sen = s_sen[j];
+                    const SensorRow sen = sen_next;
+                    sen_next = s_sen[min(j + 1, ns - 1)];
                     const double dx = bl.x - sen.x;
                     const double dy = bl.y - sen.y;
                     const double dz = bl.z - sen.z;

@@ -88,7 +88,7 @@ __device__ inline Item decode_item(const OpParams& p, int64_t item) {
     return it;
 }
 
-// Adjoint work item -> (scene, chunk of 64 balls, sensor split); items of one
+// Adjoint work item -> (scene, chunk of 256 balls, sensor split); items of one
 // scene are ordered split-major so that consecutive items share residual rows.
 struct ItemA {
     int scene, chunk, split;

@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256, OCC) void adjoint_uniform_kernel(OpParams p) {
     const float inv_delta_f = (float)p.inv_delta;
     bool geometry = false, nonfinite = false;
 
-    for (int64_t item = xcd_item(blockIdx.x, gridDim.x); item < p.n_items; item += gridDim.x) {
+    for (int64_t item = blockIdx.x; item < p.n_items; item += gridDim.x) {
         const ItemA it = decode_item_adj(p, item);
         const Scene& sc = p.scenes[it.scene];
         const int nb = min(kAdjChunk, sc.n_balls - it.chunk * kAdjChunk);

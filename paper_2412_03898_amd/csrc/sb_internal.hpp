@@ -94,16 +94,6 @@ struct ItemA {
     int scene, chunk, split;
 };
 
-// Work item of block b in a grid of n blocks.  The hardware hands blocks to the eight
-// XCDs in turn (block b to XCD b mod 8, each XCD taking its blocks in order), and each
-// XCD has its own L2; this gives XCD x the contiguous items x q + min(x, r) + i
-// (q = n / 8, r = n mod 8), so neighbouring items, which read the same trace rows,
-// share one L2.  A bijection of [0, n).
-__device__ inline int64_t xcd_item(int64_t b, int64_t n) {
-    const int64_t q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
-
 __device__ inline ItemA decode_item_adj(const OpParams& p, int64_t item) {
     int i = 0;
     while (i + 1 < p.n_scenes && p.scenes[i + 1].item0 <= item) ++i;

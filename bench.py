@@ -67,6 +67,7 @@ def workloads():
         "vessel-4d-large": synth.workload_large_ir,
         "vessel-single-frame": synth.workload_vessel_static,
         "vessel-4d": synth.workload_vessel_4d,
+        "uneven-4d-batch": synth.workload_uneven_batch,
         "plain-single-frame": synth.workload_plain,
     }
 

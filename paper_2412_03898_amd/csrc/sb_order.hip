@@ -82,7 +82,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadix = 256;
 constexpr int kSortBits = 62;                             // scene index in bits 57..61
 constexpr int kSortPasses = (kSortBits + 7) / 8;
-constexpr int kScanRows = 256;                            // tiles per column-scan block
+constexpr int kScanRows = 32;                             // tiles per column-scan block
 
 static_assert(kSortPasses % 2 == 0, "the sorted pairs land back in the input buffers");
 

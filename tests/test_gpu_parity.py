@@ -514,11 +514,11 @@ def test_order_matches_morton_definition():
 
 
 @pytest.mark.parametrize("sizes", [[1], [5, 4096, 4097], [1_100_000], [300] * 32, [0, 300, 0, 5000, 0]],
-                         ids=["one", "ragged", "two-scan-groups", "32-scenes", "empty-scenes"])
+                         ids=["one", "ragged", "nine-scan-groups", "32-scenes", "empty-scenes"])
 def test_order_ties_clamps_and_sizes(sizes):
     """Stable order with many equal keys (balls sharing a grid cell, balls clamped to the
-    grid's faces), ragged tile counts, a table of more than 256 tiles (the column scan in
-    two groups), the largest scene index and empty scenes; bit-exact against the numpy
+    grid's faces), ragged tile counts, a table of 269 tiles (the column scan in nine groups
+    of at most 32), the largest scene index and empty scenes; bit-exact against the numpy
     definition."""
     import torch
     from paper_2412_03898_amd import ops

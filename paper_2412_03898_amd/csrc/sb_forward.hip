@@ -1149,6 +1149,25 @@ __global__ __launch_bounds__(256, 4) void forward_gauss_lane_kernel(OpParams p) 
                 // next boundary's value from lane i + 1
                 auto to_row = [&](const GPair& g, int W, int tl) {
                     float x = g.xg - (float)lane;         // boundary j0 + lane (exact: integer steps)
+                    if (W <= 2 * 63) {
+                        // one or two steps: both steps' row entries are read before either is
+                        // written, so the wave waits for LDS once per window.  A step writes
+                        // only its n <= 63 samples, so lane 63 of the first step, which reads
+                        // the second step's first entry, writes nothing.
+                        const bool two = W > 63;          // the same in every lane
+                        float* const r0 = row + tl + lane;
+                        const float o0 = r0[0];
+                        const float o1 = two ? r0[63] : 0.f;
+                        const float E0 = __builtin_amdgcn_exp2f(x * x * g.ce);
+                        const float E1 = __builtin_amdgcn_exp2f((x - 63.f) * (x - 63.f) * g.ce);
+                        const float N0 = __builtin_bit_cast(
+                            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, E0), 0x130, 0xF, 0xF, false));
+                        const float N1 = __builtin_bit_cast(
+                            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, E1), 0x130, 0xF, 0xF, false));
+                        if (lane < min(63, W)) r0[0] = o0 + g.C * (N0 - E0);
+                        if (two && lane < W - 63) r0[63] = o1 + g.C * (N1 - E1);
+                        return;
+                    }
                     for (int j0 = 0; j0 < W; j0 += 63) {
                         const float E = __builtin_amdgcn_exp2f(x * x * g.ce);
                         const float En = __builtin_bit_cast(
@@ -1159,11 +1178,16 @@ __global__ __launch_bounds__(256, 4) void forward_gauss_lane_kernel(OpParams p) 
                     }
                 };
                 if (one_row) {
+                    // the next ball's pair and window length are read one ball ahead
+                    GPair gn = tab[0];                    // the same address in every lane
+                    int Wn = sball[0].Wc;
                     for (int b = 0; b < nb; ++b) {
-                        const GPair g = tab[b];           // the same address in every lane
+                        const GPair g = gn;
                         const int klo = __builtin_amdgcn_readfirstlane(g.klo);
+                        const int W = __builtin_amdgcn_readfirstlane(Wn);
+                        gn = tab[min(b + 1, nb - 1)];
+                        Wn = sball[min(b + 1, nb - 1)].Wc;
                         if (klo == INT_MIN) continue;
-                        const int W = __builtin_amdgcn_readfirstlane(sball[b].Wc);
                         if (W > kGRow) direct(g, klo, W);
                         else to_row(g, W, klo - base);
                     }

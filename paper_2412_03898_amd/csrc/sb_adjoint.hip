@@ -236,16 +236,26 @@ __global__ __launch_bounds__(256, OCC) void adjoint_gauss_kernel(OpParams p) {
                                 }
                             }
                         } else {
-                            for (int m = 0; m <= W; ++m) {
-                                const int k = klo + m;
-                                const float rm = (m < W && k >= 0 && k < p.T) ? rres[k] : 0.f;
-                                const float dr = rm - rp;
-                                rp = rm;
-                                const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
-                                A += e;
-                                Bs = fmaf(x, e, Bs);
-                                Cs = fmaf(x * x, e, Cs);
-                                x -= 1.f;
+                            // boundaries straight from global memory, eight loads in flight at
+                            // a time (no load of a batch waits on another; boundaries past W
+                            // add nothing)
+                            for (int m0 = 0; m0 <= W; m0 += 8) {
+                                float v[8];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    const int k = klo + m0 + u;
+                                    v[u] = (m0 + u < W && k >= 0 && k < p.T) ? rres[k] : 0.f;
+                                }
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    const float dr = (m0 + u <= W) ? v[u] - rp : 0.f;
+                                    rp = v[u];
+                                    const float e = __builtin_amdgcn_exp2f(x * x * ce) * dr;
+                                    A += e;
+                                    Bs = fmaf(x, e, Bs);
+                                    Cs = fmaf(x * x, e, Cs);
+                                    x -= 1.f;
+                                }
                             }
                         }
                     }

@@ -247,6 +247,28 @@ def test_adjoint_windows_outside_the_staged_row_and_at_the_record_end():
     assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
 
 
+def test_gaussian_adjoint_windows_outside_the_row_and_at_the_record_end():
+    """Gaussian balls in an order unrelated to their positions: a wave's 64 balls span the
+    whole cube, so most windows miss the wave's staged residual row and take the
+    global-memory path (eight loads at a time); the record ends 40 samples before the
+    latest window does."""
+    wl = tiny_scene(n_balls=700, n_sensors=70, seed=88, kernel=1)
+    b = wl.balls.astype(np.float64)
+    S = wl.sensors.astype(np.float64)
+    delta = wl.c / wl.fs
+    r = np.sqrt(((b[0:3, :, None] - S[:, None, :]) ** 2).sum(0))
+    h = 6.0 * b[3] / delta                       # the kernels' window half-width (6 std)
+    kl = np.floor(r / delta - wl.t0 * wl.fs - h[:, None] + 0.5).astype(int)
+    end = kl + (np.floor(2 * h).astype(int) + 2)[:, None]
+    T = int(end.max()) - 40
+    assert (end > T).sum() > 5 and (kl >= T).sum() > 0
+    wl = with_(wl, n_samples=T)
+    rng = np.random.default_rng(10)
+    res = rng.normal(size=(1, S.shape[1], T)).astype(np.float32)
+    _say(f"gaussian adjoint unordered, record cut at T={T}")
+    assert_grads(wl, gpu_adjoint(wl, res), oracle.adjoint(wl, res.astype(np.float64)))
+
+
 def _morton(wl):
     order = synth.morton_order(wl.balls)
     return with_(wl, balls=np.ascontiguousarray(wl.balls[:, order]))
